@@ -1,0 +1,161 @@
+"""Pins for the oracle's Chebyshev moments: textbook spectra, closed forms,
+exact enumeration of all Rademacher probes (CPU only)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import synthgraph as sg
+from oracle import graph as og
+from oracle import kpm
+from oracle import rng as orng
+
+
+def H_of(gen):
+    n, s, d = gen
+    g = og.build_csr(n, s, d)
+    return g, og.normalized_adjacency(g)
+
+
+def test_cycle_moments():
+    # C_n is 2-regular: H = A/2, eigenvalues cos(2 pi k / n) -> d_m = [n | m]
+    for n in (7, 8):
+        g, H = H_of(sg.cycle(n))
+        M = 30
+        mu, ldos = kpm.exact_moments_recurrence(H, M)
+        want = np.array([1.0 if m % n == 0 else 0.0 for m in range(M)])
+        assert np.allclose(mu, want, atol=1e-12)
+        assert np.allclose(ldos, want[None, :], atol=1e-12)  # vertex-transitive
+
+
+def test_path_complete_star_spectra():
+    M = 25
+    n = 9
+    _, H = H_of(sg.path(n))
+    lam = np.cos(np.pi * np.arange(n) / (n - 1))
+    assert np.allclose(kpm.exact_moments_recurrence(H, M)[0], kpm.cheb_of_eigs(lam, M).mean(1), atol=1e-12)
+    _, H = H_of(sg.complete(6))
+    lam = np.array([1.0] + [-1.0 / 5] * 5)
+    assert np.allclose(kpm.exact_moments_recurrence(H, M)[0], kpm.cheb_of_eigs(lam, M).mean(1), atol=1e-12)
+    s = 5
+    _, H = H_of(sg.star(s))
+    want = np.array([(1 + (-1) ** m + (s - 1) * np.cos(m * np.pi / 2)) / (s + 1) for m in range(M)])
+    assert np.allclose(kpm.exact_moments_recurrence(H, M)[0], want, atol=1e-12)
+
+
+@pytest.mark.parametrize("gen", [sg.complete_bipartite(3, 5), sg.path(10), sg.cycle(12), sg.star(7)])
+def test_bipartite_odd_moments_vanish(gen):
+    _, H = H_of(gen)
+    mu, ldos = kpm.exact_moments_recurrence(H, 21)
+    assert np.allclose(mu[1::2], 0.0, atol=1e-13)
+    assert np.allclose(ldos[:, 1::2], 0.0, atol=1e-13)
+
+
+def test_low_moment_closed_forms():
+    g, H = H_of(sg.erdos_renyi(400, 0.02, seed=7))
+    mu, ldos = kpm.exact_moments_recurrence(H, 3)
+    assert mu[0] == 1.0 and np.all(ldos[:, 0] == 1.0)
+    assert abs(mu[1]) < 1e-15 and np.all(np.abs(ldos[:, 1]) < 1e-15)
+    # Chebyshev d_2 = (2/N) sum_ij A_ij/(d_i d_j) - 1 = 2 tr(H^2)/N - 1
+    assert np.isclose(mu[2], 2.0 * kpm.power_moment_2(g) - 1.0, atol=1e-13)
+    assert np.allclose(ldos[:, 2], kpm.cheb_moment_2_diag(g), atol=1e-13)
+    # and the power moment itself: tr(H^2)/N by dense algebra
+    Hd = H.toarray()
+    assert np.isclose(kpm.power_moment_2(g), np.trace(Hd @ Hd) / g.n, atol=1e-13)
+
+
+@pytest.mark.parametrize("gen", [sg.erdos_renyi(300, 0.02, seed=1), sg.barabasi_albert(250, 2, seed=3, twin_pairs=10),
+                                 sg.rmat(9, 8, seed=2)])
+def test_eigh_equals_recurrence(gen):
+    _, H = H_of(gen)
+    M = 60
+    mu_e, l_e = kpm.exact_moments_eig(H, M)
+    mu_r, l_r = kpm.exact_moments_recurrence(H, M)
+    assert np.max(np.abs(mu_e - mu_r)) < 1e-10
+    assert np.max(np.abs(l_e - l_r)) < 1e-10
+
+
+def test_identity_probes_give_exact_moments():
+    _, H = H_of(sg.erdos_renyi(120, 0.05, seed=9))
+    M = 20
+    mu_r, l_r = kpm.exact_moments_recurrence(H, M)
+    mu, mu_pp, C = kpm.stochastic_moments(H, np.eye(H.shape[0]), M)
+    # with Z = I, (1/k) sum_j z_ij y_ij = T_m(H)_ii / N * ... : C = diag / N * N/k
+    assert np.allclose(C * H.shape[0], l_r, atol=1e-12)
+    assert np.allclose(mu * H.shape[0], mu_r, atol=1e-12)
+
+
+def all_sign_vectors(n):
+    return np.array(list(itertools.product([-1.0, 1.0], repeat=n))).T  # [n][2^n]
+
+
+def test_rademacher_enumeration_is_exact():
+    # averaging over every +/-1 vector makes the Hutchinson / Bekas estimators
+    # exact: E[z z^T] = I over the full set
+    _, H = H_of(sg.erdos_renyi(9, 0.5, seed=4))
+    n = H.shape[0]
+    Z = all_sign_vectors(n)
+    M = 12
+    mu, mu_pp, C = kpm.stochastic_moments(H, Z, M)
+    mu_x, l_x = kpm.exact_moments_eig(H, M)
+    assert np.allclose(mu, mu_x, atol=1e-12)
+    assert np.allclose(C, l_x, atol=1e-12)
+    assert np.allclose(mu_pp.mean(axis=0), mu_x, atol=1e-12)
+
+
+def test_rademacher_mu0_is_one():
+    g, H = H_of(sg.erdos_renyi(500, 0.01, seed=3))
+    Z = orng.rademacher(g.n, 6, seed=1)
+    mu, mu_pp, C = kpm.stochastic_moments(H, Z, 4)
+    assert np.all(mu_pp[:, 0] == 1.0) and np.all(C[:, 0] == 1.0)
+
+
+def test_variance_formulas_rademacher_exact():
+    # per-probe variance of z_i (T_m z)_i over all sign vectors = closed form
+    _, H = H_of(sg.erdos_renyi(8, 0.6, seed=12))
+    n = H.shape[0]
+    M = 6
+    mu_x, l_x = kpm.exact_moments_eig(H, 2 * M)
+    V = kpm.ldos_probe_variance(l_x, M, "rademacher")
+    Z = all_sign_vectors(n)
+    for m, Y in enumerate(kpm.cheb_vectors(H, Z, M)):
+        est = Z * Y
+        assert np.allclose(est.var(axis=1), V[:, m], atol=1e-12)
+    # a diagonal CV cannot change a Rademacher estimate at all: g (1 - z^2) = 0
+    G = np.random.default_rng(0).normal(size=(n, M))
+    _, C, _ = kpm.cv_ldos(H, Z, M, G)
+    assert np.allclose(C, l_x[:, :M], atol=1e-12)
+
+
+def test_variance_formulas_gaussian_montecarlo():
+    _, H = H_of(sg.erdos_renyi(12, 0.4, seed=5))
+    n = H.shape[0]
+    M = 5
+    mu_x, l_x = kpm.exact_moments_eig(H, 2 * M)
+    Z = orng.gaussian(n, 40000, seed=3)
+    G = l_x[:, :M] + 0.1  # an imperfect control variate
+    Vp = kpm.ldos_probe_variance(l_x, M, "gaussian")
+    Vc = kpm.ldos_probe_variance(l_x, M, "gaussian", G)
+    zz = Z * Z
+    for m, Y in enumerate(kpm.cheb_vectors(H, Z, M)):
+        plain = (Z * Y).var(axis=1)
+        cv = (G[:, m:m + 1] * (1 - zz) + Z * Y).var(axis=1)
+        assert np.allclose(plain, Vp[:, m], rtol=0.06, atol=2e-3)
+        assert np.allclose(cv, Vc[:, m], rtol=0.06, atol=2e-3)
+    # the perfect control variate g = diag T_m reaches the Rademacher variance
+    Vr = kpm.ldos_probe_variance(l_x, M, "rademacher")
+    assert np.allclose(kpm.ldos_probe_variance(l_x, M, "gaussian", l_x[:, :M]), Vr)
+
+
+def test_hutchinson_error_decays():
+    # sanity of the stochastic path on a mid-size graph: error ~ 1/sqrt(k)
+    g, H = H_of(sg.erdos_renyi(800, 0.01, seed=8))
+    M = 10
+    mu_x, _ = kpm.exact_moments_eig(H, M)
+    errs = []
+    for k in (4, 64):
+        Z = orng.rademacher(g.n, k, seed=100 + k)
+        mu, _, _ = kpm.stochastic_moments(H, Z, M, ldos=False)
+        errs.append(np.abs(mu - mu_x)[1:].max())
+    assert errs[1] < errs[0]
+    assert errs[1] < 5.0 * np.sqrt(2.0 / g.n / 64)

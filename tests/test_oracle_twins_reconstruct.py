@@ -1,0 +1,167 @@
+"""Pins for the oracle's twin classes, projection, filtered estimates and
+density reconstruction (CPU only)."""
+import itertools
+
+import numpy as np
+import pytest
+from scipy import integrate, fft
+
+import synthgraph as sg
+from oracle import graph as og
+from oracle import kpm, twins, reconstruct as rc
+
+
+def graph_of(gen):
+    n, s, d = gen
+    g = og.build_csr(n, s, d)
+    return g, og.normalized_adjacency(g)
+
+
+def brute_twins(g):
+    nb = [frozenset(g.neighbors(i).tolist()) for i in range(g.n)]
+    seen, classes = set(), []
+    for i in range(g.n):
+        if i in seen:
+            continue
+        c = [j for j in range(i, g.n) if nb[j] == nb[i]]
+        if len(c) >= 2:
+            classes.append(c)
+            seen.update(c)
+    return classes
+
+
+@pytest.mark.parametrize("gen", [sg.barabasi_albert(300, 1, seed=2, twin_pairs=20), sg.rmat(9, 4, seed=1),
+                                 sg.erdos_renyi(200, 0.008, seed=3)])
+def test_twins_match_bruteforce(gen):
+    g, _ = graph_of(gen)
+    assert twins.twin_classes(g) == brute_twins(g)
+
+
+def test_twins_textbook():
+    g, _ = graph_of(sg.star(6))
+    assert twins.twin_classes(g) == [[1, 2, 3, 4, 5, 6]]
+    g, _ = graph_of(sg.complete_bipartite(3, 4))
+    assert twins.twin_classes(g) == [[0, 1, 2], [3, 4, 5, 6]]
+    g, _ = graph_of(sg.cycle(4))
+    assert twins.twin_classes(g) == [[0, 2], [1, 3]]
+    g, _ = graph_of(sg.complete(5))     # true twins only: open neighbourhoods differ
+    assert twins.twin_classes(g) == []
+
+
+def test_twin_eigenvectors_and_projection_spectrum():
+    g, H = graph_of(sg.barabasi_albert(60, 1, seed=5, twin_pairs=6))
+    cls = twins.twin_classes(g)
+    assert cls
+    Hd = H.toarray()
+    for c in cls:
+        v = np.zeros(g.n)
+        v[c[0]], v[c[1]] = 1.0, -1.0
+        assert np.allclose(Hd @ v, 0.0, atol=1e-14)   # localized eigenvalue 0
+    P = twins.basis_dense(cls, g.n)
+    assert np.allclose(P.T @ P, np.eye(P.shape[1]), atol=1e-14)
+    lam = np.sort(np.linalg.eigvalsh(Hd))
+    lam_r = np.sort(np.linalg.eigvalsh(P.T @ Hd @ P))
+    nz = sum(len(c) - 1 for c in cls)
+    # removing nz zeros from eig(H) leaves eig(H_r)
+    rest = list(lam)
+    for _ in range(nz):
+        k = int(np.argmin(np.abs(rest)))
+        assert abs(rest[k]) < 1e-10
+        rest.pop(k)
+    assert np.allclose(np.sort(rest), lam_r, atol=1e-10)
+    PP = twins.projector_dense(cls, g.n)
+    assert np.allclose(PP @ PP, PP) and np.allclose(PP, PP.T)
+    assert np.allclose(Hd @ PP, PP @ Hd, atol=1e-14)
+    Z = np.random.default_rng(1).normal(size=(g.n, 3))
+    assert np.allclose(twins.project(Z, cls), PP @ Z)
+
+
+def test_filtered_estimates_unbiased_by_enumeration():
+    # star + pendant pair graph with twins; all 2^n sign vectors
+    n, s, d = 9, np.array([0, 0, 0, 1, 1, 2, 5, 5, 3, 4], np.int32), np.array([1, 2, 3, 4, 5, 6, 7, 8, 6, 6], np.int32)
+    g, H = graph_of((n, s, d))
+    cls = twins.twin_classes(g)
+    assert cls
+    Z = np.array(list(itertools.product([-1.0, 1.0], repeat=g.n))).T
+    M = 10
+    mu_full, mu_s, _, C = twins.filtered_moments(H, Z, M, cls)
+    mu_x, l_x = kpm.exact_moments_eig(H, M)
+    assert np.allclose(mu_full, mu_x, atol=1e-12)
+    assert np.allclose(C, l_x, atol=1e-12)
+    assert twins.spike_weight(cls, g.n) == sum(len(c) - 1 for c in cls) / g.n
+
+
+def test_arrays_canonical():
+    ptr, mem = twins.classes_to_arrays([[1, 4], [2, 3, 9]])
+    assert ptr.tolist() == [0, 2, 5] and mem.tolist() == [1, 4, 2, 3, 9]
+
+
+# ------------------------------------------------------------ reconstruction
+def test_jackson_coefficients():
+    g = rc.jackson(100)
+    assert g[0] == pytest.approx(1.0, abs=1e-15)
+    assert np.all(np.diff(g) < 0)
+    assert 0 < g[-1] < 1e-4
+
+
+def test_jackson_kernel_is_positive():
+    # the damped expansion of a point mass at x0 is non-negative (KPM review)
+    for x0 in (-0.7, 0.0, 0.33, 1.0):
+        M = 64
+        mu = np.cos(np.arange(M) * np.arccos(x0))
+        x = np.linspace(-0.999, 0.999, 2001)
+        assert rc.density(mu, x)[0].min() > -1e-12
+
+
+def test_bins_equal_quadrature_of_density():
+    g_, H = graph_of(sg.erdos_renyi(150, 0.04, seed=2))
+    M = 40
+    mu, _ = kpm.exact_moments_eig(H, M)
+    nb = 16
+    h = rc.histogram(mu, nb)[0]
+    e = rc.bin_edges(nb, -1, 1)
+    for b in range(nb):
+        q, _ = integrate.quad(lambda x: rc.density(mu, np.array([x]))[0, 0], e[b], e[b + 1], limit=200)
+        assert abs(q - h[b]) < 1e-7
+    assert abs(h.sum() - mu[0]) < 1e-13
+
+
+def test_dct3_equals_direct_sum():
+    rng = np.random.default_rng(0)
+    mu = rng.normal(size=(3, 30))
+    K = 48
+    x = rc.cheb_nodes(K)
+    direct = rc.density(mu, x) * np.pi * np.sqrt(1 - x * x)[None, :]
+    c = mu * rc.jackson(30)[None, :]
+    # DCT-III: y_k = x_0 + 2 sum_{m>=1} x_m cos(pi m (k + 1/2) / K)
+    pad = np.zeros((3, K))
+    pad[:, :30] = c
+    via_fft = fft.dct(pad, type=3, axis=1)
+    assert np.allclose(direct, via_fft, atol=1e-12)
+
+
+def test_jackson_error_bound():
+    # |int f (rho_M - mu)| <= 6 L / M for Lipschitz f (Sec. 4.1, Jackson's theorem)
+    g_, H = graph_of(sg.erdos_renyi(200, 0.05, seed=6))
+    lam = np.linalg.eigvalsh(H.toarray())
+    f = lambda x: np.abs(x - 0.3)
+    for M in (20, 80):
+        mu = kpm.cheb_of_eigs(lam, M).mean(axis=1)
+        val, _ = integrate.quad(lambda x: f(x) * rc.density(mu, np.array([x]))[0, 0], -1, 1, limit=400, points=[0.3])
+        assert abs(val - f(lam).mean()) <= 6.0 / M
+
+
+def test_exact_moment_histogram_nonnegative_and_spikes():
+    g_, H = graph_of(sg.barabasi_albert(200, 1, seed=4, twin_pairs=10))
+    mu, _ = kpm.exact_moments_eig(H, 50)
+    h = rc.histogram(mu, 50)[0]
+    assert h.min() > -1e-12
+    h2 = rc.histogram(mu, 50, spikes=[(0.0, 0.25), (1.0, 0.5), (-1.0, 0.125)])[0]
+    assert h2[25] - h[25] == pytest.approx(0.25) and h2[49] - h[49] == pytest.approx(0.5)
+    assert h2[0] - h[0] == pytest.approx(0.125)
+    assert rc.spike_bin(0.0, rc.bin_edges(100, -1, 1)) == 50
+
+
+def test_exact_histogram_snaps_edges():
+    e = rc.exact_histogram(np.array([0.0, 1e-12, -1e-12, 0.5, 1.0]), 4)
+    assert np.allclose(e, [0.0, 0.0, 0.6, 0.4], atol=1e-15)
