@@ -1,0 +1,251 @@
+/*
+ * nd.h -- C ABI of the MI355X (gfx950) network density-of-states library.
+ *
+ * The library computes, on one GPU, the kernel-polynomial-method (KPM)
+ * estimates of the spectral density of a graph's normalized adjacency
+ * H = D^{-1/2} A D^{-1/2}, following Dong, Benson & Bindel, "Network Density
+ * of States", KDD 2019:
+ *
+ *   - graph and operator: Sec. 2.1 (adjacency, degrees, normalized adjacency);
+ *   - DOS / LDOS and their Chebyshev moments: Sec. 2.2 (eqn dos, eqn ldos),
+ *     Sec. 3.1 (eq. cheb_3term, eqn doscoeff, eqn pdoscoeff);
+ *   - stochastic trace / diagonal estimation with a block of probes:
+ *     Sec. 3.1 (eq. probe_trace, eq. probe_diag);
+ *   - motif (twin) detection by hashing and probe projection: Sec. 3.4;
+ *   - Jackson-damped reconstruction and spectral histograms: Sec. 2.2
+ *     (eqn reg_dos and the histogram that follows it), Sec. 3.1 (eqn orth),
+ *     Sec. 4.1 (Jackson's theorem).
+ *
+ * Conventions
+ *   - Every entry point returns an nd_status; no exception crosses the ABI.
+ *     On a non-OK status nd_last_error() returns a thread-local message.
+ *     Inputs are validated before any kernel is launched.
+ *   - "device" pointers are HIP device memory on the current device (e.g. a
+ *     torch tensor's data_ptr()); "host" pointers are ordinary host memory.
+ *     All output buffers are owned by the caller.  Opaque handles (nd_graph,
+ *     nd_motifs) are owned by the library and released only by nd_*_free.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Moment and
+ *     reconstruction calls are asynchronous on it.  Calls that must size
+ *     allocations (nd_build_csr, nd_motif_filter) or fill host outputs
+ *     (nd_*_info, nd_*_export) synchronise the stream before returning.
+ *   - A graph handle keeps a workspace (probe blocks, recurrence state,
+ *     partial sums) that grows on demand; calls that use the same graph
+ *     handle must not overlap in time (on different streams or threads).
+ *   - Results are deterministic: the same (graph, seed, flags, sizes) give
+ *     bit-identical outputs on the same device.  No floating-point atomics.
+ *   - Node ids: the builder drops isolated nodes and renumbers the survivors
+ *     0..N-1 in ascending order of their input id; every per-node array below
+ *     (probes, LDOS rows, features) is indexed by that compact id.
+ */
+#ifndef ND_H_
+#define ND_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ND_OK = 0,
+  ND_EINVAL = -1,        /* bad argument (null pointer, size, id out of range) */
+  ND_ENOMEM = -2,        /* device allocation failed or exceeded ND_ALLOC_LIMIT_BYTES */
+  ND_EDEVICE = -3,       /* a HIP runtime call failed */
+  ND_EOVERFLOW = -4,     /* a size exceeds what the index types hold */
+  ND_EUNSUPPORTED = -5   /* valid request the library does not implement */
+} nd_status;
+
+typedef struct nd_graph nd_graph;   /* device CSR of the simple symmetric graph */
+typedef struct nd_motifs nd_motifs; /* twin classes found in a graph */
+
+/* ------------------------------------------------------------------ flags */
+#define ND_INPUT_DEVICE 0x1u      /* nd_build_csr: src/dst are device pointers */
+
+#define ND_PROBE_RADEMACHER 0x0u  /* probes with i.i.d. +/-1 entries (default) */
+#define ND_PROBE_GAUSSIAN 0x1u    /* probes with i.i.d. standard normal entries */
+#define ND_STATE_FP64 0x2u        /* run the recurrence in fp64 instead of fp32 */
+
+#define ND_TWINS_OPEN 0x1u        /* nd_motif_filter: nodes with equal open neighbourhoods */
+
+#define ND_KERNEL_NONE 0u         /* nd_reconstruct: plain truncated series */
+#define ND_KERNEL_JACKSON 1u      /* nd_reconstruct: Jackson damping factors */
+
+/* --------------------------------------------------------------- graph */
+
+/* Build the graph of Sec. 2.1 from an undirected edge list.
+ *   n_nodes  ids in src/dst must lie in [0, n_nodes); 1 <= n_nodes < 2^31.
+ *   n_edges  number of input edges, 0 <= n_edges < 2^31.
+ *   src,dst  int32 [n_edges] endpoints; host pointers, or device pointers
+ *            with ND_INPUT_DEVICE.  Read only; not retained.
+ * The edge list is symmetrised and read as a set: duplicate edges collapse
+ * to weight 1 and self-loops are dropped (the paper's operators are built
+ * from the 0/1 pattern here; weighted input is not supported).  Nodes of
+ * degree 0 are dropped (D^{-1/2} is undefined there) and the rest renumbered
+ * in ascending input-id order.  Rows list their columns in ascending order.
+ * The stored per-node scale is fp32(1/sqrt(d)) with the inverse square root
+ * taken in fp64.  On success *out owns the device CSR.
+ * Errors: ND_EINVAL (null pointer, id out of range, bad size), ND_ENOMEM,
+ * ND_EDEVICE.  Synchronises `stream`. */
+nd_status nd_build_csr(int64_t n_nodes, int64_t n_edges, const int32_t* src, const int32_t* dst,
+                       uint32_t flags, void* stream, nd_graph** out);
+
+/* Sizes of a built graph (host outputs; any may be NULL). */
+nd_status nd_graph_info(const nd_graph* g, int64_t* n, int64_t* nnz, int64_t* max_deg);
+
+/* Copy the CSR to host buffers (any may be NULL): row_ptr int64 [n+1],
+ * col int32 [nnz], old_id int32 [n] (input id of each compact node),
+ * dinv_sqrt float [n].  Synchronous. */
+nd_status nd_graph_export(const nd_graph* g, int64_t* row_ptr, int32_t* col, int32_t* old_id,
+                          float* dinv_sqrt);
+
+/* Device views of the CSR arrays (valid until nd_graph_free); any may be NULL. */
+nd_status nd_graph_device_arrays(const nd_graph* g, const int64_t** row_ptr, const int32_t** col,
+                                 const float** dinv_sqrt);
+
+void nd_graph_free(nd_graph* g);
+
+/* --------------------------------------------------------------- motifs */
+
+/* Twin detection (Sec. 3.4): nodes whose open neighbourhoods are equal share
+ * the localized eigenvectors e_i - e_j with eigenvalue 0.  Candidates come
+ * from a random hash of each neighbourhood, h_i = sum_{j in N(i)} r_j over
+ * Z/2^64 with seeded random r (the paper hashes with w = Hz); every candidate
+ * class is then confirmed by exact comparison of sorted neighbour lists, so
+ * the partition does not depend on the seed.
+ *   kinds  ND_TWINS_OPEN (the only kind implemented).
+ * Output classes (size >= 2) are in canonical order: by smallest member,
+ * members ascending.  Synchronises `stream`.
+ * Errors: ND_EINVAL, ND_EUNSUPPORTED (other kinds), ND_ENOMEM, ND_EDEVICE. */
+nd_status nd_motif_filter(const nd_graph* g, uint64_t seed, uint32_t kinds, void* stream,
+                          nd_motifs** out);
+
+/* Counts and spikes (host outputs; any may be NULL).  A twin class C removes
+ * |C|-1 eigenvalues at 0; the single spike reported is lambda = 0 with weight
+ * sum_C (|C|-1) / N (a fraction of the DOS mass).  spike_lambda/spike_weight
+ * need room for 1 entry. */
+nd_status nd_motif_info(const nd_motifs* m, int64_t* n_classes, int64_t* n_motif_nodes,
+                        int32_t* n_spikes, double* spike_lambda, double* spike_weight);
+
+/* Host copies: class_ptr int64 [n_classes+1], members int32 [n_motif_nodes]. */
+nd_status nd_motif_export(const nd_motifs* m, int64_t* class_ptr, int32_t* members);
+
+void nd_motifs_free(nd_motifs* m);
+
+/* --------------------------------------------------------------- probes */
+
+/* Write the probe block the moment calls use (for inspection and tests):
+ * Z device [n][n_probes] (node-major, fp32 values; with ND_STATE_FP64 the
+ * buffer is double).  Probe j, node i: SplitMix64 (Steele, Lea & Flood 2014)
+ * as a counter-based generator -- output n >= 1 of the stream seeded with s is
+ * mix(s + n*0x9E3779B97F4A7C15); probe j's stream is seeded with output j+1 of
+ * the stream seeded with `seed`; Rademacher takes the sign from the top bit of
+ * output i+1, Gaussian applies Box-Muller to outputs 2i+1, 2i+2 (53-bit
+ * uniforms) and rounds to fp32.  With `motifs` the block is projected
+ * (Sec. 3.4, Z_r = P P^T Z): each twin class's rows replaced by their mean. */
+nd_status nd_make_probes(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes,
+                         uint64_t seed, uint32_t flags, void* Z, void* stream);
+
+/* --------------------------------------------------------------- moments */
+
+/* Global DOS moments (Sec. 3.1, eqn doscoeff with eq. probe_trace):
+ *   mu_pp[j][m] = (1/N) z_j^T T_m(H) z_j,  mu[m] = mean_j mu_pp[j][m],
+ * m = 0..n_moments-1 (n_moments-1 sparse products per probe), by the
+ * three-term recurrence (eq. cheb_3term) applied to the whole probe block.
+ *   n_probes >= 1 (any count; blocks of up to 64 run one after another)
+ *   n_moments >= 1
+ *   flags    ND_PROBE_RADEMACHER | ND_PROBE_GAUSSIAN, optionally ND_STATE_FP64
+ *   motifs   NULL, or twin classes to filter: the probes are projected and
+ *            mu/mu_pp hold the moments of the remaining (smooth) spectrum;
+ *            the full-DOS moments are mu[m] + w T_m(0) with the spike weight
+ *            w of nd_motif_info (T_m(0) = 1, 0, -1, 0, ...).
+ *   mu       device double [n_moments]
+ *   mu_pp    device double [n_probes][n_moments], or NULL
+ * The recurrence state is fp32 (fp64 with ND_STATE_FP64); every moment is
+ * accumulated in fp64 with compensated sums in a fixed order. */
+nd_status nd_cheb_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes,
+                          int32_t n_moments, uint64_t probe_seed, uint32_t flags, double* mu,
+                          double* mu_pp, void* stream);
+
+/* Per-node LDOS / PDOS moments (Sec. 3.1, eqn pdoscoeff with eq. probe_diag):
+ *   ldos[i][m] = (1/k) sum_j v_ijm,   v_ijm = z_ij (T_m(H) z_j)_i,
+ * row-major [N][n_moments] (the matrix C of the paper's Algorithm 1 output).
+ *   cv_g     NULL, or device float [N][n_moments]: a diagonal control variate
+ *            g; then v_ijm = g_im + z_ij ((T_m(H) - diag g_m) z_j)_i, which
+ *            is unbiased for any g (with +/-1 probes it equals the plain
+ *            estimate exactly).
+ *   motifs   NULL, or twin classes: probes projected as in nd_cheb_moments,
+ *            and each class member i gets the removed part back exactly,
+ *            ldos[i][m] += (1 - 1/|C|) T_m(0), so rows stay unbiased.
+ *   ldos     device double [N][n_moments]
+ *   ldos_sq  NULL, or device double [N][n_moments]: (1/k) sum_j v_ijm^2,
+ *            for the per-probe variance ldos_sq - ldos^2.
+ *   mu       NULL, or device double [n_moments]: mean over nodes of ldos. */
+nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes,
+                          int32_t n_moments, uint64_t probe_seed, uint32_t flags,
+                          const float* cv_g, double* ldos, double* ldos_sq, double* mu,
+                          void* stream);
+
+/* --------------------------------------------------------------- reconstruction */
+
+/* Densities from moments (fp64), for each of n_rows moment vectors
+ * mu device double [n_rows][n_moments]:
+ *   series  rho(x) = [g_0 mu_0 + 2 sum_{m>=1} g_m mu_m T_m(x)] / (pi sqrt(1-x^2))
+ *           (eqn orth / eqn doscoeff), g_m the Jackson factors for M moments
+ *           g_m = [(M-m+1) cos(pi m/(M+1)) + sin(pi m/(M+1)) cot(pi/(M+1))]/(M+1)
+ *           (ND_KERNEL_JACKSON) or 1 (ND_KERNEL_NONE);
+ *   hist    device double [n_rows][n_bins] or NULL: exact integral of rho over
+ *           n_bins equal bins of [lo, hi] (-1 <= lo < hi <= 1), bins half-open
+ *           [e_b, e_{b+1}) except the last, plus point masses spike_weight[s]
+ *           at spike_lambda[s] (host arrays of n_spikes entries, may be 0);
+ *   rho     device double [n_rows][n_points] or NULL: rho at the Chebyshev
+ *           nodes x_k = cos(pi (k + 1/2) / n_points), k = 0..n_points-1. */
+nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_moments, uint32_t kernel,
+                         const double* spike_lambda, const double* spike_weight, int32_t n_spikes,
+                         int32_t n_bins, double lo, double hi, double* hist, int32_t n_points,
+                         double* rho, void* stream);
+
+/* --------------------------------------------------------------- learned control variate */
+/* Not in the paper.  A per-node MLP 5 -> 128 -> 128 -> n_out (ReLU, ReLU,
+ * linear) predicts the first n_out PDOS moments; its output is the cv_g of
+ * nd_ldos_moments.  Parameters are a flat float vector laid out
+ * [W1 (5 x 128 row-major, in x out), b1, W2 (128 x 128), b2, W3 (128 x n_out), b3].
+ * n_out must be 1..128. */
+
+/* Node features feat device float [N][5]: log1p of (degree, mean neighbour
+ * degree, max neighbour degree, local clustering 2t/(d(d-1)) (0 if d < 2),
+ * number of nodes at distance exactly 2).  If mean/std (device float [5])
+ * are given, each column is then standardised as (x - mean) / std.
+ * Needs N <= 524288 (per-node neighbourhood bitmaps live in LDS);
+ * larger graphs return ND_EUNSUPPORTED. */
+nd_status nd_node_features(const nd_graph* g, const float* mean, const float* std, float* feat,
+                           void* stream);
+
+/* Column sums over rows: out device double [2*ncol] = (sum x, sum x^2). */
+nd_status nd_column_stats(const float* x, int64_t n_rows, int32_t n_cols, double* out,
+                          void* stream);
+
+/* g device float [n][n_out] = MLP(params, feat [n][5]). */
+nd_status nd_mlp_forward(const float* params, const float* feat, int64_t n, int32_t n_out,
+                         float* g, void* stream);
+
+/* Loss and gradient of mean((MLP(feat[idx]) - target[idx])^2) over the
+ * batch rows and the n_out outputs.  idx device int32 [n] (rows of feat and
+ * target, which have ld_target columns) or NULL for rows 0..n-1.
+ * grad device float [n_params], loss device float [1].  Sums over rows are
+ * fixed-order (deterministic). */
+nd_status nd_mlp_grad(const float* params, const float* feat, const float* target,
+                      int32_t ld_target, const int32_t* idx, int64_t n, int32_t n_out,
+                      float* grad, float* loss, void* stream);
+
+/* One Adam step (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * correction with step count t >= 1) on device float arrays of n_params. */
+nd_status nd_adam_step(float* params, float* m, float* v, const float* grad, int64_t n_params,
+                       int32_t t, float lr, void* stream);
+
+/* Thread-local message for the last non-OK status ("" if none). */
+const char* nd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ND_H_ */

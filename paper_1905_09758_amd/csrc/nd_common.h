@@ -1,0 +1,174 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "nd.h"
+
+namespace nd {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;  // threads per block in every kernel of the library
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define ND_HIP(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      nd::set_error("%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return ND_EDEVICE;                                                                  \
+    }                                                                                     \
+  } while (0)
+
+#define ND_CHECK(expr)                   \
+  do {                                   \
+    nd_status s_ = (expr);               \
+    if (s_ != ND_OK) return s_;          \
+  } while (0)
+
+#define ND_REQUIRE(cond, ...)            \
+  do {                                   \
+    if (!(cond)) {                       \
+      nd::set_error(__VA_ARGS__);        \
+      return ND_EINVAL;                  \
+    }                                    \
+  } while (0)
+
+#define ND_LAUNCH_CHECK()                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = hipGetLastError();                                                        \
+    if (e_ != hipSuccess) {                                                                   \
+      nd::set_error("kernel launch: %s (%s:%d)", hipGetErrorString(e_), __FILE__, __LINE__); \
+      return ND_EDEVICE;                                                                      \
+    }                                                                                         \
+  } while (0)
+
+// Device allocation with an optional process-wide cap (environment variable
+// ND_ALLOC_LIMIT_BYTES) so that out-of-memory paths can be exercised.
+nd_status dalloc(void** p, size_t bytes);
+void dfree(void* p);
+
+template <typename T>
+nd_status dalloc_t(T** p, size_t count) {
+  return dalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+// A device buffer that only grows; freed with its owner.
+struct Scratch {
+  void* p = nullptr;
+  size_t bytes = 0;
+  nd_status ensure(size_t need) {
+    if (need <= bytes) return ND_OK;
+    dfree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t want = need + need / 8;
+    nd_status s = dalloc(&p, want);
+    if (s != ND_OK) return s;
+    bytes = want;
+    return ND_OK;
+  }
+  template <typename T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+  ~Scratch() { dfree(p); }
+};
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline int grid_for(int64_t work_items, int64_t per_block, int64_t cap = 65536) {
+  int64_t g = ceil_div(work_items, per_block);
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return static_cast<int>(g);
+}
+
+// ---------------------------------------------------------------- primitives
+// Exclusive prefix sum of n int64 values (in may alias out); returns the total
+// through *total_dev (device int64) when non-null.
+nd_status exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total_dev,
+                             hipStream_t st);
+// Same over int32 input, int64 output.
+nd_status exclusive_scan_i32_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* total_dev,
+                                 hipStream_t st);
+
+// Stable LSD radix sort of n 64-bit keys on bits [0, nbits), with an optional
+// 32-bit payload.  keys/vals are sorted in place; alt_* are scratch buffers of
+// the same size (may be swapped internally; results always end in keys/vals).
+nd_status radix_sort_u64(uint64_t* keys, uint64_t* alt_keys, uint32_t* vals, uint32_t* alt_vals,
+                         int64_t n, int nbits, hipStream_t st);
+
+// ---------------------------------------------------------------- schedule
+// Row-to-wavefront mapping for the Chebyshev sparse product, for a gathered
+// row of L 16-byte lanes.  Rows are binned by degree; bin b runs P = 2^b
+// nonzero slots per row, so one wavefront covers 64/(P*L) rows.  Rows longer
+// than one chunk (kChunkIters iterations of a full wavefront) are split into
+// chunks whose partial sums are combined in a fixed order.
+constexpr int kChunkIters = 32;
+constexpr int kMaxBins = 8;
+
+struct Schedule {
+  int L = 0;
+  int n_bins = 0;                      // sub-wave bins (P = 1 .. 64/L)
+  int64_t chunk_nnz = 0;               // nonzeros per chunk of a split row
+  int64_t bin_row_start[kMaxBins + 1] = {0};
+  int64_t bin_item_start[kMaxBins + 1] = {0};
+  int64_t n_items = 0;                 // wavefront work items, bins then chunks
+  int64_t n_split = 0, n_chunks = 0;
+  int32_t* rows = nullptr;             // [n]: rows grouped by bin, ascending inside a bin
+  int64_t* split_chunk_ptr = nullptr;  // [n_split+1]
+  int32_t* chunk_owner = nullptr;      // [n_chunks]: split-row index of each chunk
+  int32_t* split_counter = nullptr;    // [n_split], zero between launches
+  ~Schedule();
+};
+
+}  // namespace nd
+
+// ---------------------------------------------------------------- handles
+struct nd_graph {
+  int device = 0;
+  int64_t n = 0, nnz = 0, max_deg = 0;
+  int64_t* row_ptr = nullptr;  // [n+1]
+  int32_t* col = nullptr;      // [nnz]
+  int32_t* old_id = nullptr;   // [n]
+  float* dinv_sqrt = nullptr;  // [n]
+  std::map<int, std::unique_ptr<nd::Schedule>> sched;  // keyed by L
+  nd::Scratch ws_state, ws_partial, ws_chunk, ws_misc;  // moment workspaces
+  ~nd_graph();
+};
+
+struct nd_motifs {
+  int device = 0;
+  int64_t n = 0;            // nodes of the graph it belongs to
+  int64_t n_classes = 0, n_members = 0;
+  int64_t* class_ptr = nullptr;  // [n_classes+1]
+  int32_t* members = nullptr;    // [n_members]
+  double spike_weight = 0.0;     // sum_C (|C|-1) / n
+  ~nd_motifs();
+};
+
+namespace nd {
+nd_status get_schedule(nd_graph* g, int L, hipStream_t st, Schedule** out);
+}
+
+// ---------------------------------------------------------------- device helpers
+namespace nd {
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// Output n (1-based) of the SplitMix64 stream seeded with s.
+__host__ __device__ inline uint64_t splitmix64(uint64_t s, uint64_t n) { return mix64(s + n * kGamma); }
+}  // namespace nd

@@ -1,0 +1,236 @@
+"""GPU vs oracle parity through the C ABI (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import synthgraph as sg
+from oracle import graph as og
+from oracle import kpm, rng as orng, twins, reconstruct as rc
+
+pytestmark = pytest.mark.gpu
+
+TOL_MU = 1e-5          # fp32 recurrence, global moments, M <= 200
+TOL_FP64 = 1e-10
+EPS32 = 2.0 ** -24
+
+
+def ldos_tol(M, name):
+    """Per-node moments from the fp32 recurrence.  Each step rounds X to fp32
+    (relative 2^-24); an error injected at step k reaches moment m through
+    U_{m-k}(H), which is as large as m-k+1 on the eigenvalues +-1 (always
+    present: lambda = 1 is the Perron eigenvalue).  The accumulated error is
+    therefore bounded by about m^2 2^-24 where such eigenvectors put their
+    weight on a node (the star's hub); on ordinary graphs it stays below 1e-5
+    up to M = 100."""
+    if name == "star" or M > 100:
+        return max(1e-5, float(M) ** 2 * EPS32)
+    return 1e-5
+
+
+def _t(x, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
+
+
+def _zeros(n, dtype):
+    import torch
+    return torch.zeros(n, dtype=dtype, device="cuda")
+
+
+GRAPHS = {
+    "er2000": lambda: sg.erdos_renyi(2000, 0.005, seed=1),
+    "ba_twins": lambda: sg.barabasi_albert(3000, 2, seed=5, twin_pairs=150),
+    "rmat12": lambda: sg.rmat(12, 8, seed=7),
+    "star": lambda: sg.star(3000),          # one row longer than a chunk
+    "ws": lambda: sg.watts_strogatz(1500, 4, 0.3, seed=2),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(GRAPHS))
+def case(request, nd):
+    n, s, d = GRAPHS[request.param]()
+    g_or = og.build_csr(n, s, d)
+    g = nd.nd_build_csr(n, s, d)
+    return request.param, (n, s, d), g_or, g
+
+
+def test_csr_bit_exact(case, nd):
+    name, (n, s, d), g_or, g = case
+    ex = nd.nd_graph_export(g)
+    assert g.n == g_or.n and g.nnz == g_or.nnz
+    assert np.array_equal(ex["row_ptr"], g_or.row_ptr)
+    assert np.array_equal(ex["col"], g_or.col)
+    assert np.array_equal(ex["old_id"], g_or.old_id)
+    assert np.array_equal(ex["dinv_sqrt"].view(np.uint32), g_or.dinv_sqrt.view(np.uint32))
+    assert g.max_deg == int(g_or.deg.max())
+
+
+def test_csr_device_input_matches_host(case, nd):
+    import torch
+    name, (n, s, d), g_or, g = case
+    g2 = nd.nd_build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    ex = nd.nd_graph_export(g2)
+    assert np.array_equal(ex["row_ptr"], g_or.row_ptr) and np.array_equal(ex["col"], g_or.col)
+
+
+@pytest.mark.parametrize("kind", ["rademacher", "gaussian"])
+def test_probes(case, nd, kind):
+    import torch
+    name, _, g_or, g = case
+    k = 7
+    Z = _zeros(g.n * k, torch.float32)
+    flag = nd.ND_PROBE_GAUSSIAN if kind == "gaussian" else 0
+    nd.nd_make_probes(g, None, k, 1234, flag, Z)
+    got = Z.cpu().numpy().reshape(g.n, k).astype(np.float64)
+    want = orng.probes(g.n, k, 1234, kind)
+    if kind == "rademacher":
+        assert np.array_equal(got, want)
+    else:  # libm differences of an ulp before the fp32 rounding
+        assert np.max(np.abs(got - want)) <= 4e-7 * np.max(np.abs(want))
+
+
+def test_twins_bit_exact(case, nd):
+    name, _, g_or, g = case
+    m = nd.nd_motif_filter(g, seed=99)
+    ptr, mem = nd.nd_motif_export(m)
+    cls = twins.twin_classes(g_or)
+    p2, m2 = twins.classes_to_arrays(cls)
+    assert np.array_equal(ptr, p2) and np.array_equal(mem, m2)
+    if cls:
+        assert m.spikes[0][0] == 0.0
+        assert m.spikes[0][1] == pytest.approx(twins.spike_weight(cls, g_or.n), rel=0, abs=1e-15)
+
+
+@pytest.mark.parametrize("k,M", [(20, 100), (64, 60), (3, 200), (100, 30)])
+def test_global_moments(case, nd, k, M):
+    import torch
+    name, _, g_or, g = case
+    H = og.normalized_adjacency(g_or)
+    Z = orng.rademacher(g_or.n, k, 5)
+    mu_o, mupp_o, _ = kpm.stochastic_moments(H, Z, M, ldos=False)
+    mu = _zeros(M, torch.float64)
+    mupp = _zeros(k * M, torch.float64)
+    nd.nd_cheb_moments(g, None, k, M, 5, 0, mu, mupp)
+    mu, mupp = mu.cpu().numpy(), mupp.cpu().numpy().reshape(k, M)
+    assert np.all(mupp[:, 0] == 1.0)
+    assert np.max(np.abs(mu - mu_o)) < TOL_MU
+    assert np.max(np.abs(mupp - mupp_o)) < TOL_MU
+
+
+def test_global_moments_fp64_state(case, nd):
+    import torch
+    name, _, g_or, g = case
+    k, M = 16, 120
+    H = og.normalized_adjacency(g_or)
+    Z = orng.rademacher(g_or.n, k, 8)
+    mu_o, _, _ = kpm.stochastic_moments(H, Z, M, ldos=False)
+    mu = _zeros(M, torch.float64)
+    nd.nd_cheb_moments(g, None, k, M, 8, nd.ND_STATE_FP64, mu)
+    assert np.max(np.abs(mu.cpu().numpy() - mu_o)) < TOL_FP64
+
+
+@pytest.mark.parametrize("k,M", [(20, 50), (70, 12)])
+def test_ldos(case, nd, k, M):
+    import torch
+    name, _, g_or, g = case
+    H = og.normalized_adjacency(g_or)
+    Z = orng.rademacher(g_or.n, k, 11)
+    mu_o, _, C_o = kpm.stochastic_moments(H, Z, M)
+    ld = _zeros(g.n * M, torch.float64)
+    sq = _zeros(g.n * M, torch.float64)
+    mu = _zeros(M, torch.float64)
+    nd.nd_ldos_moments(g, None, k, M, 11, 0, ld, ldos_sq=sq, mu=mu)
+    C = ld.cpu().numpy().reshape(g.n, M)
+    assert np.max(np.abs(C - C_o)) < ldos_tol(M, name)
+    assert np.max(np.abs(mu.cpu().numpy() - mu_o)) < TOL_MU
+    S2_o = np.stack([(Z * Y) ** 2 for Y in kpm.cheb_vectors(H, Z, M)], axis=2).mean(axis=1)
+    assert np.max(np.abs(sq.cpu().numpy().reshape(g.n, M) - S2_o)) < 10 * ldos_tol(M, name)
+
+
+def test_filtered_moments(case, nd):
+    import torch
+    name, _, g_or, g = case
+    k, M = 24, 80
+    H = og.normalized_adjacency(g_or)
+    cls = twins.twin_classes(g_or)
+    m = nd.nd_motif_filter(g, seed=3)
+    Z = orng.rademacher(g_or.n, k, 21)
+    mu_full, mu_s, mupp_s, C = twins.filtered_moments(H, Z, M, cls)
+    mu = _zeros(M, torch.float64)
+    nd.nd_cheb_moments(g, m, k, M, 21, 0, mu)
+    assert np.max(np.abs(mu.cpu().numpy() - mu_s)) < TOL_MU
+    ld = _zeros(g.n * M, torch.float64)
+    mu2 = _zeros(M, torch.float64)
+    nd.nd_ldos_moments(g, m, k, M, 21, 0, ld, mu=mu2)
+    assert np.max(np.abs(ld.cpu().numpy().reshape(g.n, M) - C)) < ldos_tol(M, name)
+    assert np.max(np.abs(mu2.cpu().numpy() - mu_full)) < TOL_MU
+    # projected probes
+    Zd = _zeros(g.n * k, torch.float32)
+    nd.nd_make_probes(g, m, k, 21, 0, Zd)
+    Zr = twins.project(Z, cls)
+    assert np.max(np.abs(Zd.cpu().numpy().reshape(g.n, k) - Zr)) < 1e-7
+
+
+def test_control_variate_ldos(case, nd):
+    import torch
+    name, _, g_or, g = case
+    k, M = 12, 20
+    H = og.normalized_adjacency(g_or)
+    G = np.random.default_rng(0).normal(size=(g.n, M)).astype(np.float32)
+    Z = orng.gaussian(g_or.n, k, 4)
+    mu_o, C_o, S2_o = kpm.cv_ldos(H, Z, M, G.astype(np.float64))
+    ld = _zeros(g.n * M, torch.float64)
+    sq = _zeros(g.n * M, torch.float64)
+    mu = _zeros(M, torch.float64)
+    nd.nd_ldos_moments(g, None, k, M, 4, nd.ND_PROBE_GAUSSIAN, ld, cv_g=_t(G), ldos_sq=sq, mu=mu)
+    assert np.max(np.abs(ld.cpu().numpy().reshape(g.n, M) - C_o)) < 1e-4
+    assert np.max(np.abs(mu.cpu().numpy() - mu_o)) < 1e-5
+
+
+def test_deterministic(case, nd):
+    import torch
+    name, _, g_or, g = case
+    outs = []
+    for _ in range(2):
+        mu = _zeros(40, torch.float64)
+        ld = _zeros(g.n * 40, torch.float64)
+        nd.nd_ldos_moments(g, None, 33, 40, 77, 0, ld, mu=mu)
+        outs.append((mu.cpu().numpy().tobytes(), ld.cpu().numpy().tobytes()))
+    assert outs[0][0] == outs[1][0], "global moments differ between runs"
+    assert outs[0][1] == outs[1][1], "LDOS differs between runs"
+
+
+def test_reconstruct(nd):
+    import torch
+    n, s, d = sg.erdos_renyi(600, 0.01, seed=3)
+    g_or = og.build_csr(n, s, d)
+    mu, ldos = kpm.exact_moments_eig(og.normalized_adjacency(g_or), 100)
+    rows = np.vstack([mu[None, :], ldos[:50]])
+    for kernel, kname in ((nd.ND_KERNEL_JACKSON, "jackson"), (nd.ND_KERNEL_NONE, "none")):
+        for nb, lo, hi in ((100, -1.0, 1.0), (200, -1.0, 1.0), (37, -0.5, 0.8)):
+            spikes = [(0.0, 0.125), (1.0, 0.25)] if lo == -1.0 else [(0.0, 0.5)]
+            hist = _zeros(rows.shape[0] * nb, torch.float64)
+            rho = _zeros(rows.shape[0] * 64, torch.float64)
+            nd.nd_reconstruct(_t(rows), rows.shape[0], 100, kernel, spikes, nb, lo, hi, hist, 64, rho)
+            h_o = rc.histogram(rows, nb, lo, hi, kernel=kname, spikes=spikes)
+            r_o = rc.density(rows, rc.cheb_nodes(64), kernel=kname)
+            h = hist.cpu().numpy().reshape(rows.shape[0], nb)
+            assert np.max(np.abs(h - h_o).sum(axis=1)) < 1e-10
+            assert np.max(np.abs(rho.cpu().numpy().reshape(rows.shape[0], 64) - r_o)) < 1e-9
+
+
+def test_errors(nd):
+    import torch
+    with pytest.raises(nd.NDError) as e:
+        nd.nd_build_csr(3, np.array([0, 1], np.int32), np.array([1, 5], np.int32))
+    assert e.value.status == nd.ND_EINVAL
+    g = nd.nd_build_csr(4, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
+    with pytest.raises(nd.NDError) as e:
+        nd.nd_motif_filter(g, 1, kinds=0x4)
+    assert e.value.status == nd.ND_EUNSUPPORTED
+    mu = _zeros(4, torch.float64)
+    with pytest.raises(nd.NDError):
+        nd.nd_cheb_moments(g, None, 0, 4, 1, 0, mu)
+    empty = nd.nd_build_csr(4, np.array([2], np.int32), np.array([2], np.int32))
+    assert empty.n == 0 and empty.nnz == 0
+    with pytest.raises(nd.NDError):
+        nd.nd_cheb_moments(empty, None, 4, 4, 1, 0, mu)
