@@ -64,11 +64,16 @@ typedef struct nd_motifs nd_motifs; /* twin classes found in a graph */
 #define ND_PROBE_RADEMACHER 0x0u  /* probes with i.i.d. +/-1 entries (default) */
 #define ND_PROBE_GAUSSIAN 0x1u    /* probes with i.i.d. standard normal entries */
 #define ND_STATE_FP64 0x2u        /* run the recurrence in fp64 instead of fp32 */
+#define ND_TIME_STEPS 0x4u        /* time each sparse-product step launch with HIP events
+                                     (read back with nd_graph_step_timing; adds a
+                                     host synchronisation at the end of the call) */
 
 #define ND_TWINS_OPEN 0x1u        /* nd_motif_filter: nodes with equal open neighbourhoods */
 
 #define ND_KERNEL_NONE 0u         /* nd_reconstruct: plain truncated series */
 #define ND_KERNEL_JACKSON 1u      /* nd_reconstruct: Jackson damping factors */
+#define ND_SPIKES_IN_MOMENTS 0x10u /* nd_reconstruct: the moments include the spikes;
+                                     subtract w T_m(lambda) before the smooth part */
 
 /* --------------------------------------------------------------- graph */
 
@@ -101,6 +106,10 @@ nd_status nd_graph_export(const nd_graph* g, int64_t* row_ptr, int32_t* col, int
 /* Device views of the CSR arrays (valid until nd_graph_free); any may be NULL. */
 nd_status nd_graph_device_arrays(const nd_graph* g, const int64_t** row_ptr, const int32_t** col,
                                  const float** dinv_sqrt);
+
+/* Total HIP-event time (ms) and count of the sparse-product step launches of
+ * the last nd_cheb_moments / nd_ldos_moments call made with ND_TIME_STEPS. */
+nd_status nd_graph_step_timing(const nd_graph* g, double* total_ms, int64_t* launches);
 
 void nd_graph_free(nd_graph* g);
 

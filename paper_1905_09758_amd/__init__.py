@@ -22,16 +22,17 @@ LIB_PATH = os.path.join(_HERE, "libnd.so")
 
 ND_OK, ND_EINVAL, ND_ENOMEM, ND_EDEVICE, ND_EOVERFLOW, ND_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ND_INPUT_DEVICE = 0x1
-ND_PROBE_RADEMACHER, ND_PROBE_GAUSSIAN, ND_STATE_FP64 = 0x0, 0x1, 0x2
+ND_PROBE_RADEMACHER, ND_PROBE_GAUSSIAN, ND_STATE_FP64, ND_TIME_STEPS = 0x0, 0x1, 0x2, 0x4
 ND_TWINS_OPEN = 0x1
-ND_KERNEL_NONE, ND_KERNEL_JACKSON = 0, 1
+ND_KERNEL_NONE, ND_KERNEL_JACKSON, ND_SPIKES_IN_MOMENTS = 0, 1, 0x10
 
 _STATUS = {ND_EINVAL: "ND_EINVAL", ND_ENOMEM: "ND_ENOMEM", ND_EDEVICE: "ND_EDEVICE",
            ND_EOVERFLOW: "ND_EOVERFLOW", ND_EUNSUPPORTED: "ND_EUNSUPPORTED"}
 
 # every symbol the C header declares (checked by the CPU test suite)
 EXPORTS = (
-    "nd_build_csr", "nd_graph_info", "nd_graph_export", "nd_graph_device_arrays", "nd_graph_free",
+    "nd_build_csr", "nd_graph_info", "nd_graph_export", "nd_graph_device_arrays", "nd_graph_step_timing",
+    "nd_graph_free",
     "nd_motif_filter", "nd_motif_info", "nd_motif_export", "nd_motifs_free", "nd_make_probes",
     "nd_cheb_moments", "nd_ldos_moments", "nd_reconstruct", "nd_node_features", "nd_column_stats",
     "nd_mlp_forward", "nd_mlp_grad", "nd_adam_step", "nd_last_error",
@@ -68,6 +69,7 @@ _sig("nd_build_csr", [_i64, _i64, _vp, _vp, _u32, _vp, _P(_vp)])
 _sig("nd_graph_info", [_vp, _P(_i64), _P(_i64), _P(_i64)])
 _sig("nd_graph_export", [_vp, _vp, _vp, _vp, _vp])
 _sig("nd_graph_device_arrays", [_vp, _P(_vp), _P(_vp), _P(_vp)])
+_sig("nd_graph_step_timing", [_vp, _P(_dbl), _P(_i64)])
 _sig("nd_graph_free", [_vp], None)
 _sig("nd_motif_filter", [_vp, _u64, _u32, _vp, _P(_vp)])
 _sig("nd_motif_info", [_vp, _P(_i64), _P(_i64), _P(_i32), _P(_dbl), _P(_dbl)])
@@ -196,6 +198,13 @@ def nd_build_csr(n_nodes: int, src, dst, stream=None) -> Graph:
 
 def nd_graph_info(g: Graph):
     return g.n, g.nnz, g.max_deg
+
+
+def nd_graph_step_timing(g: Graph):
+    """(total ms, launches) of the step kernels of the last call made with ND_TIME_STEPS."""
+    ms, n = _dbl(), _i64()
+    _check(_lib.nd_graph_step_timing(g.handle, ctypes.byref(ms), ctypes.byref(n)), "nd_graph_step_timing")
+    return ms.value, n.value
 
 
 def nd_graph_export(g: Graph) -> dict:

@@ -16,6 +16,7 @@
 // X_{m+1} overwrites X_{m-1} in place: row i reads only its own old row.
 #include <cmath>
 #include <cstdlib>
+#include <vector>
 
 #include "nd_common.h"
 
@@ -58,6 +59,36 @@ __device__ inline void store16(T* p, const T (&v)[16 / sizeof(T)]) {
   *reinterpret_cast<V*>(p) = x;
 }
 
+// Streaming (non-temporal) 16-byte accesses for data touched once per step
+// (the X_{m-1} / X_{m+1} rows and the probe rows), so that cache capacity
+// stays with the gathered rows of X_m.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ inline void load16_nt(const T* p, T (&v)[16 / sizeof(T)]) {
+  if constexpr (sizeof(T) == 4) {
+    const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+  } else {
+    const f64x2 x = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
+    v[0] = x[0]; v[1] = x[1];
+  }
+}
+
+template <typename T>
+__device__ inline void store16_nt(T* p, const T (&v)[16 / sizeof(T)]) {
+  if constexpr (sizeof(T) == 4) {
+    f32x4 x;
+    x[0] = v[0]; x[1] = v[1]; x[2] = v[2]; x[3] = v[3];
+    __builtin_nontemporal_store(x, reinterpret_cast<f32x4*>(p));
+  } else {
+    f64x2 x;
+    x[0] = v[0]; x[1] = v[1];
+    __builtin_nontemporal_store(x, reinterpret_cast<f64x2*>(p));
+  }
+}
+
 // Neumaier-compensated accumulation.
 __device__ inline void neumaier(double& s, double& c, double x) {
   const double t = s + x;
@@ -66,54 +97,52 @@ __device__ inline void neumaier(double& s, double& c, double x) {
 }
 
 struct StepArgs {
-  const int64_t* row_ptr;
+  const int64_t* row_ptr;  // internal CSR
   const int32_t* col;
-  const int32_t* rows;
+  const int32_t* perm;     // internal row -> compact node id (LDOS / control-variate rows)
   int64_t n;
   int n_bins;
+  int bin_log2p[kMaxBins];
   int64_t bin_row_start[kMaxBins + 1];
   int64_t bin_item_start[kMaxBins + 1];
+  int64_t n_chunks;        // items [0, n_chunks) are chunks of the split rows
   int64_t n_items;
   const int64_t* split_chunk_ptr;
   const int32_t* chunk_owner;
-  int32_t* split_counter;
   int64_t chunk_nnz;
+  int64_t n_split;         // split rows are internal rows [0, n_split)
   void* chunk_part;
   const void* xg;   // X_m, gathered
   void* xio;        // X_{m-1} in, X_{m+1} out
-  const void* z;    // probe block (projected when filtering)
+  const void* z;    // probe block in internal row order (projected when filtering)
   int first;        // step m == 1: X_1 = D^{-1} A X_0
   int kp;           // padded probes per row
   int k_batch;      // real probes in this block
   double inv_k;     // 1 / (total probe count over all blocks)
   int m;            // moment index written by this launch
   double* partial;  // [gridDim.x + n_split][kp] per-probe partial sums for moment m
-  int64_t n_split;  // rows split into chunks (one partial slot each)
-  double* ldos;     // [n][ld] or null
+  double* ldos;     // [n][ld] (compact node order) or null
   double* ldos_sq;  // [n][ld] or null
   int64_t ld;       // leading dimension of ldos / cv_g (= number of moments)
   int accumulate;   // add to ldos instead of overwriting (later probe blocks)
   const float* cv_g;
 };
 
-// Per-row epilogue: given Y_m(i, probes of this lane) in fp64, form the
-// estimator terms v_ij = z_ij y_ij (+ g_im (1 - z_ij^2) with a control
-// variate), add them to this lane's per-probe accumulators, and write the
-// row's LDOS entry.  Called by every lane of the wavefront; `own` selects the
-// lanes that hold a row's values.
-// With `direct` set (rows split over several wavefronts) the terms go to that
-// row's own partial slot instead, so the summation order does not depend on
-// which wavefront finished the row.
+// Per-row epilogue: given Y_m(i, probes of this lane) in fp64 and the probe
+// values z, form the estimator terms v_ij = z_ij y_ij (+ g_im (1 - z_ij^2)
+// with a control variate), add them to this lane's per-probe sums, and write
+// the row's LDOS entry.  Called by every lane of the wavefront; `own` selects
+// the lanes that hold a row's values.  With `direct` set (rows split over
+// several wavefronts) the terms go to that row's own partial slot instead, so
+// the summation order does not depend on which wavefront finished the row.
 template <typename T, int L>
-__device__ inline void emit_moments(const StepArgs& a, bool own, int64_t r, const double (&y)[16 / sizeof(T)],
-                                    int q, double (&acc_s)[16 / sizeof(T)], double (&acc_c)[16 / sizeof(T)],
+__device__ inline void emit_moments(const StepArgs& a, bool own, int64_t node, const double (&y)[16 / sizeof(T)],
+                                    const T (&z)[16 / sizeof(T)], int q, double (&acc)[16 / sizeof(T)],
                                     double* direct = nullptr) {
   constexpr int PPL = 16 / sizeof(T);
   double s1 = 0.0, s2 = 0.0;
   if (own) {
-    T z[PPL];
-    load16<T>(reinterpret_cast<const T*>(a.z) + r * a.kp + q * PPL, z);
-    const double g = a.cv_g ? static_cast<double>(a.cv_g[r * a.ld + a.m]) : 0.0;
+    const double g = a.cv_g ? static_cast<double>(a.cv_g[node * a.ld + a.m]) : 0.0;
 #pragma unroll
     for (int c = 0; c < PPL; ++c) {
       const double zc = static_cast<double>(z[c]);
@@ -123,7 +152,7 @@ __device__ inline void emit_moments(const StepArgs& a, bool own, int64_t r, cons
       if (direct)
         direct[q * PPL + c] = v;
       else
-        neumaier(acc_s[c], acc_c[c], v);
+        acc[c] += v;
       s1 += v;
       s2 += v * v;
     }
@@ -135,21 +164,45 @@ __device__ inline void emit_moments(const StepArgs& a, bool own, int64_t r, cons
       s2 += __shfl_xor(s2, off, kWave);
     }
     if (own && q == 0) {
-      double* p = a.ldos + r * a.ld + a.m;
+      double* p = a.ldos + node * a.ld + a.m;
       *p = (a.accumulate ? *p : 0.0) + s1 * a.inv_k;
       if (a.ldos_sq) {
-        double* p2 = a.ldos_sq + r * a.ld + a.m;
+        double* p2 = a.ldos_sq + node * a.ld + a.m;
         *p2 = (a.accumulate ? *p2 : 0.0) + s2 * a.inv_k;
       }
     }
   }
 }
 
-// Finish row r: X_{m+1} = 2/d * acc - X_{m-1} (or acc/d on the first step),
-// store it in place, then the moment epilogue on Y = sqrt(d) X.
+// The per-row operands that do not depend on the gathers: X_{m-1}(r), the
+// probe values and the node id.  Issued before the gathers so that their
+// latency overlaps with them.
+template <typename T>
+struct RowOperands {
+  T xp[16 / sizeof(T)];
+  T z[16 / sizeof(T)];
+  int64_t node;
+};
+
+template <typename T>
+__device__ inline void load_row_operands(const StepArgs& a, bool own, int64_t r, int q, RowOperands<T>& o) {
+  constexpr int PPL = 16 / sizeof(T);
+  o.node = 0;
+#pragma unroll
+  for (int c = 0; c < PPL; ++c) o.xp[c] = o.z[c] = T(0);
+  if (own) {
+    if (!a.first) load16_nt<T>(reinterpret_cast<const T*>(a.xio) + r * a.kp + q * PPL, o.xp);
+    load16_nt<T>(reinterpret_cast<const T*>(a.z) + r * a.kp + q * PPL, o.z);
+    if (a.ldos || a.cv_g) o.node = a.perm[r];
+  }
+}
+
+// Finish row r: X_{m+1} = 2/d * acc - X_{m-1} (or acc/d on the first step)
+// evaluated in the accumulator type A, stored in place, then the moment
+// epilogue on Y = sqrt(d) X.
 template <typename T, int L, typename A>
 __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_t d, const A (&acc)[16 / sizeof(T)],
-                                  int q, double (&acc_s)[16 / sizeof(T)], double (&acc_c)[16 / sizeof(T)],
+                                  const RowOperands<T>& o, int q, double (&mom)[16 / sizeof(T)],
                                   double* direct = nullptr) {
   constexpr int PPL = 16 / sizeof(T);
   double y[PPL];
@@ -161,13 +214,11 @@ __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_
 #pragma unroll
       for (int c = 0; c < PPL; ++c) xn[c] = static_cast<T>(acc[c] * invd);
     } else {
-      T xp[PPL];
-      load16<T>(xo, xp);
       const A two_invd = A(2) * invd;
 #pragma unroll
-      for (int c = 0; c < PPL; ++c) xn[c] = static_cast<T>(two_invd * acc[c] - static_cast<A>(xp[c]));
+      for (int c = 0; c < PPL; ++c) xn[c] = static_cast<T>(two_invd * acc[c] - static_cast<A>(o.xp[c]));
     }
-    store16<T>(xo, xn);
+    store16_nt<T>(xo, xn);
     const double sd = sqrt(static_cast<double>(d));
 #pragma unroll
     for (int c = 0; c < PPL; ++c) y[c] = static_cast<double>(xn[c]) * sd;
@@ -175,104 +226,130 @@ __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_
 #pragma unroll
     for (int c = 0; c < PPL; ++c) y[c] = 0.0;
   }
-  emit_moments<T, L>(a, own, r, y, q, acc_s, acc_c, direct);
+  emit_moments<T, L>(a, own, o.node, y, o.z, q, mom, direct);
 }
 
-// Rows of a sub-wave bin: P nonzero slots per row, 64/(P*L) rows per wavefront.
+// Sum of X rows over the nonzeros e0+sub, e0+sub+P, ... < e1: four
+// independent gathers in flight per lane (predicated), added in a fixed order.
+template <typename T, int P>
+__device__ inline void gather_sum(const StepArgs& a, int64_t e0, int64_t e1, int sub, int q,
+                                  T (&acc)[16 / sizeof(T)]) {
+  constexpr int PPL = 16 / sizeof(T);
+  const T* xg = reinterpret_cast<const T*>(a.xg);
+  const int64_t kp = a.kp;
+  for (int64_t e = e0 + sub; e < e1; e += 4 * P) {
+    int64_t j[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      j[u] = (e + u * P < e1) ? static_cast<int64_t>(__builtin_nontemporal_load(a.col + e + u * P)) : -1;
+    T v[4][PPL];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (j[u] >= 0) {
+        load16<T>(xg + j[u] * kp + q * PPL, v[u]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < PPL; ++c) v[u][c] = T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < PPL; ++c) acc[c] += v[u][c];
+  }
+}
+
+// Rows of one bin: P nonzero slots per row, 64/(P*L) consecutive rows per wavefront.
 template <typename T, int L, int P>
 __device__ inline void rows_item(const StepArgs& a, int bin, int64_t local_item, int lane,
-                                 double (&acc_s)[16 / sizeof(T)], double (&acc_c)[16 / sizeof(T)]) {
+                                 double (&mom)[16 / sizeof(T)]) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int G = P * L;
   constexpr int RPW = kWave / G;
   const int grp = lane / G, sub = (lane % G) / L, q = lane % L;
-  const int64_t ridx = a.bin_row_start[bin] + local_item * RPW + grp;
-  const bool active = ridx < a.bin_row_start[bin + 1];
-  const int64_t r = active ? a.rows[ridx] : 0;
+  const int64_t r = a.bin_row_start[bin] + local_item * RPW + grp;
+  const bool active = r < a.bin_row_start[bin + 1];
+  const bool own = active && sub == 0;
   const int64_t e0 = active ? a.row_ptr[r] : 0, e1 = active ? a.row_ptr[r + 1] : 0;
+  RowOperands<T> o;
+  load_row_operands<T>(a, own, r, q, o);
   T acc[PPL];
 #pragma unroll
   for (int c = 0; c < PPL; ++c) acc[c] = T(0);
-  const T* xg = reinterpret_cast<const T*>(a.xg);
-  for (int64_t e = e0 + sub; e < e1; e += P) {
-    const int64_t j = a.col[e];
-    T v[PPL];
-    load16<T>(xg + j * a.kp + q * PPL, v);
-#pragma unroll
-    for (int c = 0; c < PPL; ++c) acc[c] += v[c];
-  }
+  gather_sum<T, P>(a, e0, e1, sub, q, acc);
 #pragma unroll
   for (int off = L; off < G; off <<= 1)
 #pragma unroll
     for (int c = 0; c < PPL; ++c) acc[c] += __shfl_xor(acc[c], off, kWave);
-  finish_row<T, L, T>(a, active && sub == 0, r, e1 - e0, acc, q, acc_s, acc_c);
+  finish_row<T, L, T>(a, own, r, e1 - e0, acc, o, q, mom);
 }
 
-// One chunk of a long row; the wavefront that completes the row's last chunk
-// sums the chunk partials in chunk order and finishes the row.
+// One chunk of a split row: its partial sum (fp64) goes to the chunk's slot.
+// The rows are finished by k_split_finish after the step kernel, so no
+// device-wide fence is needed here.
 template <typename T, int L>
-__device__ inline void chunk_item(const StepArgs& a, int64_t c, int lane, double (&acc_s)[16 / sizeof(T)],
-                                  double (&acc_c)[16 / sizeof(T)]) {
+__device__ inline void chunk_item(const StepArgs& a, int64_t c, int lane) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int P = kWave / L;
   const int sub = lane / L, q = lane % L;
-  const int64_t s = a.chunk_owner[c];
-  const int64_t r = a.rows[a.bin_row_start[a.n_bins] + s];
-  const int64_t c0 = a.split_chunk_ptr[s], nch = a.split_chunk_ptr[s + 1] - c0;
+  const int64_t r = a.chunk_owner[c];
+  const int64_t c0 = a.split_chunk_ptr[r];
   const int64_t rb = a.row_ptr[r], re = a.row_ptr[r + 1];
   const int64_t e0 = rb + (c - c0) * a.chunk_nnz;
   const int64_t e1 = e0 + a.chunk_nnz < re ? e0 + a.chunk_nnz : re;
   T acc[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) acc[k] = T(0);
-  const T* xg = reinterpret_cast<const T*>(a.xg);
-  for (int64_t e = e0 + sub; e < e1; e += P) {
-    const int64_t j = a.col[e];
-    T v[PPL];
-    load16<T>(xg + j * a.kp + q * PPL, v);
-#pragma unroll
-    for (int k = 0; k < PPL; ++k) acc[k] += v[k];
-  }
+  gather_sum<T, P>(a, e0, e1, sub, q, acc);
 #pragma unroll
   for (int off = L; off < kWave; off <<= 1)
 #pragma unroll
     for (int k = 0; k < PPL; ++k) acc[k] += __shfl_xor(acc[k], off, kWave);
-  // chunk partials are kept in fp64: a long row sums many of them
   double* part = reinterpret_cast<double*>(a.chunk_part);
   if (sub == 0) {
 #pragma unroll
     for (int k = 0; k < PPL; ++k) part[c * a.kp + q * PPL + k] = static_cast<double>(acc[k]);
   }
-  __threadfence();
-  int old = 0;
-  if (lane == 0) old = atomicAdd(&a.split_counter[s], 1);
-  old = __shfl(old, 0, kWave);
-  if (old == nch - 1) {
-    __threadfence();
+}
+
+// Split rows: one wavefront per row sums the row's chunk partials (slot s of
+// the wavefront takes chunks s, s+P, ... in order, then a fixed xor tree) and
+// finishes the row; the row's moment terms go to its own partial slot.
+template <typename T, int L>
+__global__ __launch_bounds__(kBlock) void k_split_finish(StepArgs a, int step_grid) {
+  constexpr int PPL = 16 / sizeof(T);
+  constexpr int P = kWave / L;
+  const int lane = threadIdx.x & (kWave - 1), sub = lane / L, q = lane % L;
+  double unused[PPL];
+  const double* part = reinterpret_cast<const double*>(a.chunk_part);
+  for (int64_t r = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; r < a.n_split;
+       r += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
+    const int64_t c0 = a.split_chunk_ptr[r], c1 = a.split_chunk_ptr[r + 1];
+    RowOperands<T> o;
+    load_row_operands<T>(a, sub == 0, r, q, o);
     double tot[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) tot[k] = 0.0;
-    if (sub == 0) {
-      for (int64_t cc = 0; cc < nch; ++cc) {
+    for (int64_t c = c0 + sub; c < c1; c += P)
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) tot[k] += part[(c0 + cc) * a.kp + q * PPL + k];
-      }
-    }
-    finish_row<T, L, double>(a, sub == 0, r, re - rb, tot, q, acc_s, acc_c,
-                             a.partial + (static_cast<int64_t>(gridDim.x) + s) * a.kp);
-    if (lane == 0) a.split_counter[s] = 0;
+      for (int k = 0; k < PPL; ++k) tot[k] += part[c * a.kp + q * PPL + k];
+#pragma unroll
+    for (int off = L; off < kWave; off <<= 1)
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) tot[k] += __shfl_xor(tot[k], off, kWave);
+    finish_row<T, L, double>(a, sub == 0, r, a.row_ptr[r + 1] - a.row_ptr[r], tot, o, q, unused,
+                             a.partial + (static_cast<int64_t>(step_grid) + r) * a.kp);
   }
 }
 
-// Block-level fixed-order reduction of the per-lane probe accumulators into
+// Block-level fixed-order reduction of the per-lane probe sums into
 // partial[blockIdx.x][0..kp).
 template <typename T, int L>
-__device__ inline void block_partials(const StepArgs& a, const double (&acc_s)[16 / sizeof(T)],
-                                      const double (&acc_c)[16 / sizeof(T)]) {
+__device__ inline void block_partials(const StepArgs& a, const double (&mom)[16 / sizeof(T)]) {
   constexpr int PPL = 16 / sizeof(T);
   __shared__ double red[kBlock][PPL];
 #pragma unroll
-  for (int c = 0; c < PPL; ++c) red[threadIdx.x][c] = acc_s[c] + acc_c[c];
+  for (int c = 0; c < PPL; ++c) red[threadIdx.x][c] = mom[c];
   __syncthreads();
   if (static_cast<int>(threadIdx.x) < a.kp) {
     const int j = threadIdx.x, qq = j / PPL, cc = j % PPL;
@@ -287,72 +364,68 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int PMAX = kWave / L;
   const int lane = threadIdx.x & (kWave - 1);
-  double acc_s[PPL], acc_c[PPL];
+  double mom[PPL];
 #pragma unroll
-  for (int c = 0; c < PPL; ++c) acc_s[c] = acc_c[c] = 0.0;
+  for (int c = 0; c < PPL; ++c) mom[c] = 0.0;
   const int64_t n_waves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
   for (int64_t it = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave; it < a.n_items;
        it += n_waves) {
+    if (it < a.n_chunks) {
+      chunk_item<T, L>(a, it, lane);
+      continue;
+    }
+    const int64_t li = it - a.n_chunks;
     int b = 0;
-    while (b < a.n_bins && it >= a.bin_item_start[b + 1]) ++b;
-    if (b < a.n_bins) {
-      const int64_t li = it - a.bin_item_start[b];
-      switch (b) {
+    while (b + 1 < a.n_bins && li >= a.bin_item_start[b + 1]) ++b;
+    const int64_t bi = li - a.bin_item_start[b];
+    switch (a.bin_log2p[b]) {
 #define ND_BIN(B) \
   case B:         \
-    if constexpr ((1 << B) <= PMAX) rows_item<T, L, (1 << B)>(a, b, li, lane, acc_s, acc_c); \
+    if constexpr ((1 << B) <= PMAX) rows_item<T, L, (1 << B)>(a, b, bi, lane, mom); \
     break;
-        ND_BIN(0)
-        ND_BIN(1)
-        ND_BIN(2)
-        ND_BIN(3)
-        ND_BIN(4)
-        ND_BIN(5)
-        ND_BIN(6)
+      ND_BIN(0)
+      ND_BIN(1)
+      ND_BIN(2)
+      ND_BIN(3)
+      ND_BIN(4)
+      ND_BIN(5)
+      ND_BIN(6)
 #undef ND_BIN
-        default:
-          break;
-      }
-    } else {
-      chunk_item<T, L>(a, it - a.bin_item_start[a.n_bins], lane, acc_s, acc_c);
+      default:
+        break;
     }
   }
-  block_partials<T, L>(a, acc_s, acc_c);
+  block_partials<T, L>(a, mom);
 }
 
-// Moment 0: Y_0 = Z.  Rows in natural order, 64/L rows per wavefront.
+// Moment 0: Y_0 = Z.  Internal rows in order, 64/L rows per wavefront.
 template <typename T, int L>
 __global__ __launch_bounds__(kBlock) void k_moment0(StepArgs a) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int RPW = kWave / L;
   const int lane = threadIdx.x & (kWave - 1), q = lane % L, grp = lane / L;
-  double acc_s[PPL], acc_c[PPL];
+  double mom[PPL];
 #pragma unroll
-  for (int c = 0; c < PPL; ++c) acc_s[c] = acc_c[c] = 0.0;
+  for (int c = 0; c < PPL; ++c) mom[c] = 0.0;
   const int64_t n_waves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
   const int64_t items = ceil_div(a.n, RPW);
   for (int64_t it = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave; it < items;
        it += n_waves) {
     const int64_t r = it * RPW + grp;
     const bool own = r < a.n;
+    RowOperands<T> o;
+    load_row_operands<T>(a, own, r, q, o);
     double y[PPL];
-    if (own) {
-      T z[PPL];
-      load16<T>(reinterpret_cast<const T*>(a.z) + r * a.kp + q * PPL, z);
 #pragma unroll
-      for (int c = 0; c < PPL; ++c) y[c] = static_cast<double>(z[c]);
-    } else {
-#pragma unroll
-      for (int c = 0; c < PPL; ++c) y[c] = 0.0;
-    }
-    emit_moments<T, L>(a, own, own ? r : 0, y, q, acc_s, acc_c);
+    for (int c = 0; c < PPL; ++c) y[c] = static_cast<double>(o.z[c]);
+    emit_moments<T, L>(a, own, o.node, y, o.z, q, mom);
   }
   // no split rows at moment 0: clear their slots
   double* sp = a.partial + static_cast<int64_t>(gridDim.x) * a.kp;
   for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < a.n_split * a.kp;
        t += static_cast<int64_t>(gridDim.x) * kBlock)
     sp[t] = 0.0;
-  block_partials<T, L>(a, acc_s, acc_c);
+  block_partials<T, L>(a, mom);
 }
 
 }  // namespace
@@ -377,18 +450,21 @@ __device__ inline float probe_value(uint64_t seed, int64_t j, int64_t i, bool ga
   return static_cast<float>(g);
 }
 
-// Z[i][ld] (probes j0 .. j0+k_batch-1 in columns 0..k_batch-1, zeros beyond)
-// and, when X0 is given, X0 = D^{-1/2} Z.
+// Z[r][ld] (probes j0 .. j0+k_batch-1 in columns 0..k_batch-1, zeros beyond)
+// for rows r of an ordering whose node ids are perm[r] (identity if null);
+// when X0 is given, X0 = D^{-1/2} Z with degrees from that ordering's row_ptr.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_probes(int64_t n, int ld, int k_batch, int64_t j0, uint64_t seed,
                                                    int gaussian, const int64_t* __restrict__ row_ptr,
-                                                   T* __restrict__ Z, T* __restrict__ X0) {
+                                                   const int32_t* __restrict__ perm, T* __restrict__ Z,
+                                                   T* __restrict__ X0) {
   const int64_t total = n * ld;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; idx < total;
        idx += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int64_t i = idx / ld;
     const int j = static_cast<int>(idx - i * ld);
-    const T z = j < k_batch ? static_cast<T>(probe_value(seed, j0 + j, i, gaussian != 0)) : T(0);
+    const int64_t node = perm ? static_cast<int64_t>(perm[i]) : i;
+    const T z = j < k_batch ? static_cast<T>(probe_value(seed, j0 + j, node, gaussian != 0)) : T(0);
     Z[idx] = z;
     if (X0) {
       const double d = static_cast<double>(row_ptr[i + 1] - row_ptr[i]);
@@ -399,12 +475,14 @@ __global__ __launch_bounds__(kBlock) void k_probes(int64_t n, int ld, int k_batc
 
 // Twin projection Z <- P P^T Z (Sec. 3.4): each class's rows replaced by the
 // class mean (fp64 sum in member order).  Members of a class share their
-// neighbourhood and hence their degree.
+// neighbourhood and hence their degree.  Member node i lives in row inv[i]
+// (row i if inv is null).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_project(const int64_t* __restrict__ class_ptr,
                                                     const int32_t* __restrict__ members, int64_t n_classes,
                                                     int ld, int k_batch, const int64_t* __restrict__ row_ptr,
-                                                    T* __restrict__ Z, T* __restrict__ X0) {
+                                                    const int32_t* __restrict__ inv, T* __restrict__ Z,
+                                                    T* __restrict__ X0) {
   const int64_t total = n_classes * k_batch;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; idx < total;
        idx += static_cast<int64_t>(gridDim.x) * kBlock) {
@@ -412,10 +490,13 @@ __global__ __launch_bounds__(kBlock) void k_project(const int64_t* __restrict__ 
     const int j = static_cast<int>(idx - c * k_batch);
     const int64_t p0 = class_ptr[c], p1 = class_ptr[c + 1];
     double s = 0.0;
-    for (int64_t p = p0; p < p1; ++p) s += static_cast<double>(Z[static_cast<int64_t>(members[p]) * ld + j]);
+    for (int64_t p = p0; p < p1; ++p) {
+      const int64_t i = inv ? static_cast<int64_t>(inv[members[p]]) : static_cast<int64_t>(members[p]);
+      s += static_cast<double>(Z[i * ld + j]);
+    }
     const T mean = static_cast<T>(s / static_cast<double>(p1 - p0));
     for (int64_t p = p0; p < p1; ++p) {
-      const int64_t i = members[p];
+      const int64_t i = inv ? static_cast<int64_t>(inv[members[p]]) : static_cast<int64_t>(members[p]);
       Z[i * ld + j] = mean;
       if (X0) {
         const double d = static_cast<double>(row_ptr[i + 1] - row_ptr[i]);
@@ -483,13 +564,57 @@ int pow2_at_least(int x) {
   return p;
 }
 
-int step_grid_cap() {
-  static int cap = [] {
-    const char* e = std::getenv("ND_STEP_GRID");
-    int v = e ? std::atoi(e) : 0;
-    return v > 0 ? v : 2048;
+// Resident blocks of the step kernel on the whole device (occupancy times
+// compute units): the persistent grid of the sparse product.  ND_STEP_GRID
+// overrides it (tuning experiments).
+template <typename T, int L>
+int resident_grid() {
+  static int grid = [] {
+    if (const char* e = std::getenv("ND_STEP_GRID")) {
+      const int v = std::atoi(e);
+      if (v > 0) return v;
+    }
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cheb_step<T, L>, kBlock, 0) != hipSuccess ||
+        cus <= 0 || per_cu <= 0) {
+      (void)hipGetLastError();
+      return 2048;
+    }
+    return cus * per_cu;
   }();
-  return cap;
+  return grid;
+}
+
+template <typename T>
+int step_grid(int L) {
+  switch (L) {
+    case 1: return resident_grid<T, 1>();
+    case 2: return resident_grid<T, 2>();
+    case 4: return resident_grid<T, 4>();
+    case 8: return resident_grid<T, 8>();
+    case 16: return resident_grid<T, 16>();
+    case 32:
+      if constexpr (sizeof(T) == 8) return resident_grid<T, 32>();
+      break;
+    default: break;
+  }
+  return 2048;
+}
+
+// Probes per block of the recurrence (a power of two, at most 64);
+// ND_MAX_BLOCK_PROBES lowers it (tuning experiments).
+int max_block_probes() {
+  static int v = [] {
+    int b = 64;
+    if (const char* e = std::getenv("ND_MAX_BLOCK_PROBES")) {
+      const int x = std::atoi(e);
+      if (x >= 1 && x <= 64) b = pow2_at_least(x);
+    }
+    return b;
+  }();
+  return v;
 }
 
 struct MomentJob {
@@ -503,14 +628,21 @@ struct MomentJob {
   double* mu = nullptr;
   double* mu_pp = nullptr;
   double spike_w = 0.0;  // added to mu as w T_m(0)
+  bool timed = false;
 };
 
 template <typename T, int L>
 nd_status launch_step_kernels(const StepArgs& base, int grid, bool moment0, hipStream_t st) {
-  if (moment0)
+  if (moment0) {
     hipLaunchKernelGGL((k_moment0<T, L>), dim3(grid), dim3(kBlock), 0, st, base);
-  else
+  } else {
     hipLaunchKernelGGL((k_cheb_step<T, L>), dim3(grid), dim3(kBlock), 0, st, base);
+    if (base.n_split > 0) {
+      ND_LAUNCH_CHECK();
+      const int g2 = grid_for(base.n_split, kWavesPerBlock, grid);
+      hipLaunchKernelGGL((k_split_finish<T, L>), dim3(g2), dim3(kBlock), 0, st, base, grid);
+    }
+  }
   ND_LAUNCH_CHECK();
   return ND_OK;
 }
@@ -538,23 +670,36 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
   const int64_t N = g->n;
   const int M = job.M;
   double* mu_pp = job.mu_pp;
+  std::vector<hipEvent_t> evs;
+  if (job.timed) {
+    g->step_ms = 0.0;
+    g->step_launches = 0;
+  }
+  struct EvFree {
+    std::vector<hipEvent_t>& e;
+    ~EvFree() {
+      for (hipEvent_t x : e) (void)hipEventDestroy(x);
+    }
+  } ev_free{evs};
   if (!mu_pp) {
     ND_CHECK(g->ws_misc.ensure(static_cast<size_t>(job.k) * M * sizeof(double)));
     mu_pp = g->ws_misc.as<double>();
   }
-  for (int j0 = 0; j0 < job.k; j0 += 64) {
-    const int kb = job.k - j0 < 64 ? job.k - j0 : 64;
+  const int bmax = max_block_probes();
+  for (int j0 = 0; j0 < job.k; j0 += bmax) {
+    const int kb = job.k - j0 < bmax ? job.k - j0 : bmax;
     const int kp = pow2_at_least(kb < PPL ? PPL : kb);
     const int L = kp * static_cast<int>(sizeof(T)) / 16;
     Schedule* sc = nullptr;
     ND_CHECK(get_schedule(g, L, st, &sc));
+    Internal* in = g->internal.get();
     const size_t blk = static_cast<size_t>(N) * kp * sizeof(T);
     ND_CHECK(g->ws_state.ensure(3 * blk));
     ND_CHECK(g->ws_chunk.ensure(static_cast<size_t>(sc->n_chunks > 0 ? sc->n_chunks : 1) * kp * sizeof(double)));
     T* Z = g->ws_state.as<T>();
     T* A = Z + static_cast<int64_t>(N) * kp;
     T* B = A + static_cast<int64_t>(N) * kp;
-    const int grid = grid_for(sc->n_items > 0 ? sc->n_items : 1, kWavesPerBlock, step_grid_cap());
+    const int grid = grid_for(sc->n_items > 0 ? sc->n_items : 1, kWavesPerBlock, step_grid<T>(L));
     const int64_t slots = static_cast<int64_t>(grid) + sc->n_split;
     const int64_t per_step = slots * kp;
     int R = static_cast<int>((int64_t(64) << 20) / (per_step * 8));
@@ -564,28 +709,29 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     double* partial = g->ws_partial.as<double>();
 
     hipLaunchKernelGGL(k_probes<T>, dim3(grid_for(N * kp, kBlock)), dim3(kBlock), 0, st, N, kp, kb,
-                       static_cast<int64_t>(j0), job.seed, job.gaussian ? 1 : 0, g->row_ptr, Z, A);
+                       static_cast<int64_t>(j0), job.seed, job.gaussian ? 1 : 0, in->row_ptr, in->perm, Z, A);
     ND_LAUNCH_CHECK();
     if (job.motifs && job.motifs->n_classes > 0) {
       hipLaunchKernelGGL(k_project<T>, dim3(grid_for(job.motifs->n_classes * kb, kBlock)), dim3(kBlock), 0, st,
-                         job.motifs->class_ptr, job.motifs->members, job.motifs->n_classes, kp, kb, g->row_ptr,
-                         Z, A);
+                         job.motifs->class_ptr, job.motifs->members, job.motifs->n_classes, kp, kb, in->row_ptr,
+                         in->inv, Z, A);
       ND_LAUNCH_CHECK();
     }
     StepArgs a{};
-    a.row_ptr = g->row_ptr;
-    a.col = g->col;
-    a.rows = sc->rows;
+    a.row_ptr = in->row_ptr;
+    a.col = in->col;
+    a.perm = in->perm;
     a.n = N;
     a.n_bins = sc->n_bins;
     for (int b = 0; b <= kMaxBins; ++b) {
       a.bin_row_start[b] = sc->bin_row_start[b];
       a.bin_item_start[b] = sc->bin_item_start[b];
+      if (b < kMaxBins) a.bin_log2p[b] = sc->bin_log2p[b];
     }
+    a.n_chunks = sc->n_chunks;
     a.n_items = sc->n_items;
     a.split_chunk_ptr = sc->split_chunk_ptr;
     a.chunk_owner = sc->chunk_owner;
-    a.split_counter = sc->split_counter;
     a.chunk_nnz = sc->chunk_nnz;
     a.n_split = sc->n_split;
     a.chunk_part = g->ws_chunk.p;
@@ -602,12 +748,24 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
       a.m = m;
       a.partial = partial + static_cast<int64_t>(m % R) * per_step;
       if (m == 0) {
+        a.first = 1;  // no X_{m-1} operand at moment 0
+        a.xg = nullptr;
+        a.xio = nullptr;
         ND_CHECK(launch_step<T>(L, a, grid, true, st));
       } else {
         a.first = (m == 1) ? 1 : 0;
         a.xg = (m & 1) ? A : B;
         a.xio = (m & 1) ? B : A;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (job.timed) {
+          ND_HIP(hipEventCreate(&e0));
+          evs.push_back(e0);
+          ND_HIP(hipEventCreate(&e1));
+          evs.push_back(e1);
+          ND_HIP(hipEventRecord(e0, st));
+        }
         ND_CHECK(launch_step<T>(L, a, grid, false, st));
+        if (job.timed) ND_HIP(hipEventRecord(e1, st));
       }
       if ((m + 1) % R == 0 || m == M - 1) {
         const int m0 = m - (m % R);
@@ -615,6 +773,15 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
                            1.0 / static_cast<double>(N), mu_pp, M, static_cast<int64_t>(j0));
         ND_LAUNCH_CHECK();
       }
+    }
+  }
+  if (job.timed) {
+    ND_HIP(hipStreamSynchronize(st));
+    for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+      float ms = 0.f;
+      ND_HIP(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
+      g->step_ms += ms;
+      g->step_launches++;
     }
   }
   if (job.mu) {
@@ -637,7 +804,8 @@ nd_status check_common(const nd_graph* g, const nd_motifs* motifs, int32_t n_pro
   ND_REQUIRE(g->n > 0, "%s: the graph has no edges (no node survives)", who);
   ND_REQUIRE(n_probes >= 1, "%s: n_probes=%d must be >= 1", who, n_probes);
   ND_REQUIRE(n_moments >= 1, "%s: n_moments=%d must be >= 1", who, n_moments);
-  ND_REQUIRE((flags & ~(ND_PROBE_GAUSSIAN | ND_STATE_FP64)) == 0, "%s: unknown flags 0x%x", who, flags);
+  ND_REQUIRE((flags & ~(ND_PROBE_GAUSSIAN | ND_STATE_FP64 | ND_TIME_STEPS)) == 0, "%s: unknown flags 0x%x", who,
+             flags);
   ND_REQUIRE(motifs == nullptr || motifs->n == g->n, "%s: motifs belong to another graph", who);
   int dev = -1;
   ND_HIP(hipGetDevice(&dev));
@@ -662,11 +830,11 @@ nd_status nd_make_probes(const nd_graph* g, const nd_motifs* motifs, int32_t n_p
   if (flags & ND_STATE_FP64) {
     hipLaunchKernelGGL(nd::k_probes<double>, dim3(nd::grid_for(total, nd::kBlock)), dim3(nd::kBlock), 0, st, g->n,
                        n_probes, n_probes, int64_t(0), seed, gaussian ? 1 : 0, g->row_ptr,
-                       static_cast<double*>(Z), static_cast<double*>(nullptr));
+                       static_cast<const int32_t*>(nullptr), static_cast<double*>(Z), static_cast<double*>(nullptr));
   } else {
     hipLaunchKernelGGL(nd::k_probes<float>, dim3(nd::grid_for(total, nd::kBlock)), dim3(nd::kBlock), 0, st, g->n,
                        n_probes, n_probes, int64_t(0), seed, gaussian ? 1 : 0, g->row_ptr,
-                       static_cast<float*>(Z), static_cast<float*>(nullptr));
+                       static_cast<const int32_t*>(nullptr), static_cast<float*>(Z), static_cast<float*>(nullptr));
   }
   ND_LAUNCH_CHECK();
   if (motifs && motifs->n_classes > 0) {
@@ -674,11 +842,11 @@ nd_status nd_make_probes(const nd_graph* g, const nd_motifs* motifs, int32_t n_p
     if (flags & ND_STATE_FP64)
       hipLaunchKernelGGL(nd::k_project<double>, dim3(nd::grid_for(t2, nd::kBlock)), dim3(nd::kBlock), 0, st,
                          motifs->class_ptr, motifs->members, motifs->n_classes, n_probes, n_probes, g->row_ptr,
-                         static_cast<double*>(Z), static_cast<double*>(nullptr));
+                         static_cast<const int32_t*>(nullptr), static_cast<double*>(Z), static_cast<double*>(nullptr));
     else
       hipLaunchKernelGGL(nd::k_project<float>, dim3(nd::grid_for(t2, nd::kBlock)), dim3(nd::kBlock), 0, st,
                          motifs->class_ptr, motifs->members, motifs->n_classes, n_probes, n_probes, g->row_ptr,
-                         static_cast<float*>(Z), static_cast<float*>(nullptr));
+                         static_cast<const int32_t*>(nullptr), static_cast<float*>(Z), static_cast<float*>(nullptr));
     ND_LAUNCH_CHECK();
   }
   return ND_OK;
@@ -697,6 +865,7 @@ nd_status nd_cheb_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
   job.gaussian = (flags & ND_PROBE_GAUSSIAN) != 0;
   job.mu = mu;
   job.mu_pp = mu_pp;
+  job.timed = (flags & ND_TIME_STEPS) != 0;
   nd_graph* gm = const_cast<nd_graph*>(g);
   if (flags & ND_STATE_FP64) return nd::run_moments<double>(gm, job, nd::as_stream(stream));
   return nd::run_moments<float>(gm, job, nd::as_stream(stream));
@@ -719,6 +888,7 @@ nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
   job.ldos_sq = ldos_sq;
   job.mu = mu;
   job.spike_w = motifs ? motifs->spike_weight : 0.0;
+  job.timed = (flags & ND_TIME_STEPS) != 0;
   nd_graph* gm = const_cast<nd_graph*>(g);
   if (flags & ND_STATE_FP64) return nd::run_moments<double>(gm, job, nd::as_stream(stream));
   return nd::run_moments<float>(gm, job, nd::as_stream(stream));

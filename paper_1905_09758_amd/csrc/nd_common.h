@@ -63,6 +63,20 @@ nd_status dalloc_t(T** p, size_t count) {
   return dalloc(reinterpret_cast<void**>(p), count * sizeof(T));
 }
 
+// Temporaries of one call, freed together (hipFree waits for the device).
+struct Tmp {
+  std::vector<void*> ptrs;
+  template <typename T>
+  nd_status get(T** p, size_t count) {
+    ND_CHECK(dalloc_t(p, count));
+    ptrs.push_back(*p);
+    return ND_OK;
+  }
+  ~Tmp() {
+    for (void* p : ptrs) dfree(p);
+  }
+};
+
 // A device buffer that only grows; freed with its owner.
 struct Scratch {
   void* p = nullptr;
@@ -110,26 +124,37 @@ nd_status radix_sort_u64(uint64_t* keys, uint64_t* alt_keys, uint32_t* vals, uin
                          int64_t n, int nbits, hipStream_t st);
 
 // ---------------------------------------------------------------- schedule
-// Row-to-wavefront mapping for the Chebyshev sparse product, for a gathered
-// row of L 16-byte lanes.  Rows are binned by degree; bin b runs P = 2^b
-// nonzero slots per row, so one wavefront covers 64/(P*L) rows.  Rows longer
-// than one chunk (kChunkIters iterations of a full wavefront) are split into
-// chunks whose partial sums are combined in a fixed order.
+// The sparse product runs on an internal numbering of the rows by descending
+// degree (ties by ascending id): long rows first, then rows of decreasing
+// length, so that rows of one length class are a contiguous range and the
+// most-gathered rows (the high-degree ones) share cache lines.
+struct Internal {
+  int32_t* perm = nullptr;     // [n] internal row -> compact node id
+  int32_t* inv = nullptr;      // [n] compact node id -> internal row
+  int64_t* row_ptr = nullptr;  // [n+1]
+  int32_t* col = nullptr;      // [nnz] internal column ids
+  ~Internal();
+};
+
+// Row-to-wavefront mapping for a gathered row of L 16-byte lanes.  A row of
+// degree d gets P = 2^b nonzero slots, b = clamp(ceil(log2(ceil(d/4))), 0,
+// log2(64/L)), so one wavefront covers 64/(P*L) rows; rows longer than one
+// chunk (kChunkIters iterations of a full wavefront) are split into chunks
+// whose fp64 partial sums a second kernel combines in a fixed order.
 constexpr int kChunkIters = 32;
 constexpr int kMaxBins = 8;
 
 struct Schedule {
   int L = 0;
-  int n_bins = 0;                      // sub-wave bins (P = 1 .. 64/L)
-  int64_t chunk_nnz = 0;               // nonzeros per chunk of a split row
-  int64_t bin_row_start[kMaxBins + 1] = {0};
-  int64_t bin_item_start[kMaxBins + 1] = {0};
-  int64_t n_items = 0;                 // wavefront work items, bins then chunks
-  int64_t n_split = 0, n_chunks = 0;
-  int32_t* rows = nullptr;             // [n]: rows grouped by bin, ascending inside a bin
+  int n_bins = 0;                      // non-empty bins, in internal row order
+  int bin_log2p[kMaxBins] = {0};
+  int64_t bin_row_start[kMaxBins + 1] = {0};   // internal row ranges
+  int64_t bin_item_start[kMaxBins + 1] = {0};  // wavefront items after the chunks
+  int64_t chunk_nnz = 0;
+  int64_t n_split = 0, n_chunks = 0;   // split rows are internal rows [0, n_split)
+  int64_t n_items = 0;                 // n_chunks + bin items
   int64_t* split_chunk_ptr = nullptr;  // [n_split+1]
-  int32_t* chunk_owner = nullptr;      // [n_chunks]: split-row index of each chunk
-  int32_t* split_counter = nullptr;    // [n_split], zero between launches
+  int32_t* chunk_owner = nullptr;      // [n_chunks]
   ~Schedule();
 };
 
@@ -143,8 +168,13 @@ struct nd_graph {
   int32_t* col = nullptr;      // [nnz]
   int32_t* old_id = nullptr;   // [n]
   float* dinv_sqrt = nullptr;  // [n]
+  std::unique_ptr<nd::Internal> internal;              // built on first use
   std::map<int, std::unique_ptr<nd::Schedule>> sched;  // keyed by L
   nd::Scratch ws_state, ws_partial, ws_chunk, ws_misc;  // moment workspaces
+  // ND_TIME_STEPS: HIP-event time of the sparse-product step launches of the
+  // last moment call (the launches of moment 1 .. M-1 of every probe block)
+  double step_ms = 0.0;
+  int64_t step_launches = 0;
   ~nd_graph();
 };
 
@@ -159,6 +189,7 @@ struct nd_motifs {
 };
 
 namespace nd {
+nd_status get_internal(nd_graph* g, hipStream_t st, Internal** out);
 nd_status get_schedule(nd_graph* g, int L, hipStream_t st, Schedule** out);
 }
 

@@ -55,13 +55,6 @@ void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
-Schedule::~Schedule() {
-  dfree(rows);
-  dfree(split_chunk_ptr);
-  dfree(chunk_owner);
-  dfree(split_counter);
-}
-
 namespace {
 
 // ------------------------------------------------------------------ build kernels
@@ -170,19 +163,6 @@ int bit_length(int64_t x) {
   return b;
 }
 
-// RAII for build temporaries
-struct Tmp {
-  std::vector<void*> ptrs;
-  template <typename T>
-  nd_status get(T** p, size_t count) {
-    ND_CHECK(dalloc_t(p, count));
-    ptrs.push_back(*p);
-    return ND_OK;
-  }
-  ~Tmp() {
-    for (void* p : ptrs) dfree(p);
-  }
-};
 
 nd_status build_impl(int64_t n_nodes, int64_t m, const int32_t* src_in, const int32_t* dst_in,
                      uint32_t flags, hipStream_t st, nd_graph* g) {
@@ -274,132 +254,7 @@ nd_status build_impl(int64_t n_nodes, int64_t m, const int32_t* src_in, const in
   return ND_OK;
 }
 
-// ------------------------------------------------------------------ schedule kernels
-__device__ inline int ceil_log2_dev(int64_t x) {
-  int b = 0;
-  while ((int64_t(1) << b) < x) b++;
-  return b;
-}
-
-__global__ __launch_bounds__(kBlock) void k_bin_keys(const int64_t* __restrict__ row_ptr, int64_t n,
-                                                     int log2_pmax, int64_t chunk_nnz,
-                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                     unsigned long long* __restrict__ bin_count) {
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const int64_t d = row_ptr[i + 1] - row_ptr[i];
-    int b;
-    if (d > chunk_nnz) {
-      b = log2_pmax + 1;
-    } else {
-      b = ceil_log2_dev((d + 3) / 4);
-      if (b > log2_pmax) b = log2_pmax;
-    }
-    keys[i] = static_cast<uint64_t>(b);
-    vals[i] = static_cast<uint32_t>(i);
-  }
-  // bin counts, aggregated per wavefront before the atomics
-  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock; base < n;
-       base += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const int64_t i = base + threadIdx.x;
-    const int b = i < n ? static_cast<int>(keys[i]) : -1;
-    for (int t = 0; t <= log2_pmax + 1; ++t) {
-      const unsigned long long c = __popcll(__ballot(b == t));
-      if ((threadIdx.x & (kWave - 1)) == 0 && c) atomicAdd(&bin_count[t], c);
-    }
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_split_chunks(const int64_t* __restrict__ row_ptr,
-                                                         const uint32_t* __restrict__ rows, int64_t n_split,
-                                                         int64_t chunk_nnz, int64_t* __restrict__ nch) {
-  for (int64_t s = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; s < n_split;
-       s += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const int64_t r = rows[s];
-    const int64_t d = row_ptr[r + 1] - row_ptr[r];
-    nch[s] = (d + chunk_nnz - 1) / chunk_nnz;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_chunk_owner(const int64_t* __restrict__ ptr, int64_t n_split,
-                                                        int32_t* __restrict__ owner) {
-  for (int64_t s = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; s < n_split;
-       s += static_cast<int64_t>(gridDim.x) * kBlock)
-    for (int64_t c = ptr[s]; c < ptr[s + 1]; ++c) owner[c] = static_cast<int32_t>(s);
-}
-
 }  // namespace
-
-nd_status get_schedule(nd_graph* g, int L, hipStream_t st, Schedule** out) {
-  auto it = g->sched.find(L);
-  if (it != g->sched.end()) {
-    *out = it->second.get();
-    return ND_OK;
-  }
-  std::unique_ptr<Schedule> s(new Schedule());
-  s->L = L;
-  const int pmax = kWave / L;
-  int log2_pmax = 0;
-  while ((1 << log2_pmax) < pmax) log2_pmax++;
-  s->n_bins = log2_pmax + 1;
-  s->chunk_nnz = static_cast<int64_t>(pmax) * kChunkIters;
-  const int64_t n = g->n;
-  ND_CHECK(dalloc_t(&s->rows, static_cast<size_t>(n > 0 ? n : 1)));
-  unsigned long long hcount[kMaxBins + 1] = {0};
-  if (n > 0) {
-    Tmp t;
-    uint64_t *keys, *akeys;
-    uint32_t* avals;
-    unsigned long long* cnt;
-    ND_CHECK(t.get(&keys, static_cast<size_t>(n)));
-    ND_CHECK(t.get(&akeys, static_cast<size_t>(n)));
-    ND_CHECK(t.get(&avals, static_cast<size_t>(n)));
-    ND_CHECK(t.get(&cnt, kMaxBins + 1));
-    ND_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (kMaxBins + 1), st));
-    hipLaunchKernelGGL(k_bin_keys, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, g->row_ptr, n, log2_pmax,
-                       s->chunk_nnz, keys, reinterpret_cast<uint32_t*>(s->rows), cnt);
-    ND_LAUNCH_CHECK();
-    ND_CHECK(radix_sort_u64(keys, akeys, reinterpret_cast<uint32_t*>(s->rows), avals, n, 4, st));
-    ND_HIP(hipMemcpyAsync(hcount, cnt, sizeof(hcount), hipMemcpyDeviceToHost, st));
-    ND_HIP(hipStreamSynchronize(st));
-  }
-  int64_t row = 0, item = 0;
-  for (int b = 0; b < s->n_bins; ++b) {
-    s->bin_row_start[b] = row;
-    s->bin_item_start[b] = item;
-    const int64_t rpw = kWave / ((int64_t(1) << b) * L);
-    row += static_cast<int64_t>(hcount[b]);
-    item += ceil_div(static_cast<int64_t>(hcount[b]), rpw);
-  }
-  s->bin_row_start[s->n_bins] = row;
-  s->bin_item_start[s->n_bins] = item;
-  s->n_split = static_cast<int64_t>(hcount[s->n_bins]);
-  if (s->n_split > 0) {
-    Tmp t;
-    int64_t *nch, *tot;
-    ND_CHECK(t.get(&nch, static_cast<size_t>(s->n_split)));
-    ND_CHECK(t.get(&tot, 1));
-    ND_CHECK(dalloc_t(&s->split_chunk_ptr, static_cast<size_t>(s->n_split + 1)));
-    hipLaunchKernelGGL(k_split_chunks, dim3(grid_for(s->n_split, kBlock)), dim3(kBlock), 0, st, g->row_ptr,
-                       reinterpret_cast<const uint32_t*>(s->rows) + row, s->n_split, s->chunk_nnz, nch);
-    ND_LAUNCH_CHECK();
-    ND_CHECK(exclusive_scan_i64(nch, s->split_chunk_ptr, s->n_split, tot, st));
-    ND_HIP(hipMemcpyAsync(s->split_chunk_ptr + s->n_split, tot, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
-    ND_HIP(hipMemcpyAsync(&s->n_chunks, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    ND_HIP(hipStreamSynchronize(st));
-    ND_CHECK(dalloc_t(&s->chunk_owner, static_cast<size_t>(s->n_chunks)));
-    ND_CHECK(dalloc_t(&s->split_counter, static_cast<size_t>(s->n_split)));
-    ND_HIP(hipMemsetAsync(s->split_counter, 0, static_cast<size_t>(s->n_split) * 4, st));
-    hipLaunchKernelGGL(k_chunk_owner, dim3(grid_for(s->n_split, kBlock)), dim3(kBlock), 0, st,
-                       s->split_chunk_ptr, s->n_split, s->chunk_owner);
-    ND_LAUNCH_CHECK();
-    ND_HIP(hipStreamSynchronize(st));
-  }
-  s->n_items = item + s->n_chunks;
-  *out = s.get();
-  g->sched[L] = std::move(s);
-  return ND_OK;
-}
 
 }  // namespace nd
 
@@ -463,6 +318,14 @@ nd_status nd_graph_device_arrays(const nd_graph* g, const int64_t** row_ptr, con
   if (row_ptr) *row_ptr = g->row_ptr;
   if (col) *col = g->col;
   if (dinv_sqrt) *dinv_sqrt = g->dinv_sqrt;
+  return ND_OK;
+}
+
+nd_status nd_graph_step_timing(const nd_graph* g, double* total_ms, int64_t* launches) {
+  nd::clear_error();
+  ND_REQUIRE(g != nullptr, "nd_graph_step_timing: graph is NULL");
+  if (total_ms) *total_ms = g->step_ms;
+  if (launches) *launches = g->step_launches;
   return ND_OK;
 }
 

@@ -176,18 +176,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter_members(const int64_t* __res
   }
 }
 
-struct Tmp {
-  std::vector<void*> ptrs;
-  template <typename T>
-  nd_status get(T** p, size_t count) {
-    ND_CHECK(dalloc_t(p, count));
-    ptrs.push_back(*p);
-    return ND_OK;
-  }
-  ~Tmp() {
-    for (void* p : ptrs) dfree(p);
-  }
-};
 
 nd_status twins_impl(const nd_graph* g, uint64_t seed, hipStream_t st, nd_motifs* out) {
   const int64_t n = g->n;

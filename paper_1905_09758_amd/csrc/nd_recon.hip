@@ -52,7 +52,8 @@ constexpr int kMaxStage = 1024;  // moments staged per pass
 
 __global__ __launch_bounds__(kBlock) void k_recon_apply(const double* __restrict__ mu, int64_t n_rows, int M,
                                                         const double* __restrict__ W, int ncols,
-                                                        double* __restrict__ out, int ld_out) {
+                                                        double* __restrict__ out, int ld_out,
+                                                        const double* __restrict__ corr) {
   __shared__ double smu[kRows][kMaxStage];
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kRows;
   const int work = kRows * ncols;
@@ -81,7 +82,25 @@ __global__ __launch_bounds__(kBlock) void k_recon_apply(const double* __restrict
     const int w = threadIdx.x + u * kBlock;
     if (w >= work) break;
     const int rr = w / ncols, c = w % ncols;
-    if (r0 + rr < n_rows) out[(r0 + rr) * ld_out + c] = acc[u];
+    if (r0 + rr < n_rows) out[(r0 + rr) * ld_out + c] = corr ? acc[u] - corr[c] : acc[u];
+  }
+}
+
+// corr[c] = sum_s w_s sum_m T_m(lambda_s) W[c][m]: the part of column c that
+// the point masses contribute when the moments include them.
+__global__ __launch_bounds__(kBlock) void k_spike_corr(const double* __restrict__ W, int ncols, int M,
+                                                       const double* __restrict__ lam, const double* __restrict__ w,
+                                                       int n_spikes, double* __restrict__ corr) {
+  for (int c = blockIdx.x * kBlock + threadIdx.x; c < ncols; c += gridDim.x * kBlock) {
+    double acc = 0.0;
+    for (int s = 0; s < n_spikes; ++s) {
+      const double x = lam[s] < -1.0 ? -1.0 : (lam[s] > 1.0 ? 1.0 : lam[s]);
+      const double th = acos(x);
+      double t = 0.0;
+      for (int m = 0; m < M; ++m) t = fma(cos(static_cast<double>(m) * th), W[static_cast<int64_t>(c) * M + m], t);
+      acc += w[s] * t;
+    }
+    corr[c] = acc;
   }
 }
 
@@ -115,6 +134,8 @@ extern "C" nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_
   ND_REQUIRE(mu != nullptr, "nd_reconstruct: mu is NULL");
   ND_REQUIRE(n_rows >= 1 && n_moments >= 1, "nd_reconstruct: n_rows=%lld n_moments=%d", (long long)n_rows,
              n_moments);
+  const bool spikes_in = (kernel & ND_SPIKES_IN_MOMENTS) != 0;
+  kernel &= ~ND_SPIKES_IN_MOMENTS;
   ND_REQUIRE(kernel == ND_KERNEL_NONE || kernel == ND_KERNEL_JACKSON, "nd_reconstruct: unknown kernel %u", kernel);
   ND_REQUIRE(hist || rho, "nd_reconstruct: hist and rho are both NULL");
   ND_REQUIRE(!hist || (n_bins >= 1 && n_bins <= 4096), "nd_reconstruct: n_bins=%d not in [1, 4096]", n_bins);
@@ -145,9 +166,19 @@ extern "C" nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_
     sbin.push_back(b);
     sw.push_back(spike_weight[s]);
   }
-  double *W = nullptr, *F = nullptr, *sw_d = nullptr;
+  double *W = nullptr, *F = nullptr, *sw_d = nullptr, *corr = nullptr, *all_d = nullptr;
   int32_t* sb_d = nullptr;
   nd_status s = dalloc_t(&W, static_cast<size_t>(ncols) * n_moments);
+  if (s == ND_OK && spikes_in && n_spikes > 0) {
+    s = dalloc_t(&corr, static_cast<size_t>(ncols));
+    if (s == ND_OK) s = dalloc_t(&all_d, static_cast<size_t>(2 * n_spikes));
+    if (s == ND_OK &&
+        (hipMemcpyAsync(all_d, spike_lambda, n_spikes * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+         hipMemcpyAsync(all_d + n_spikes, spike_weight, n_spikes * 8, hipMemcpyHostToDevice, st) != hipSuccess)) {
+      set_error("nd_reconstruct: copy of spikes failed");
+      s = ND_EDEVICE;
+    }
+  }
   if (s == ND_OK && nb) s = dalloc_t(&F, static_cast<size_t>(n_rows) * n_edges);
   if (s == ND_OK && !sbin.empty()) s = dalloc_t(&sb_d, sbin.size());
   if (s == ND_OK && !sw.empty()) s = dalloc_t(&sw_d, sw.size());
@@ -161,21 +192,25 @@ extern "C" nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_
   if (s == ND_OK) {
     hipLaunchKernelGGL(k_recon_table, dim3(grid_for(static_cast<int64_t>(ncols) * n_moments, kBlock)), dim3(kBlock),
                        0, st, n_moments, static_cast<int>(kernel), nb, lo, hi, np, W);
+    if (corr)
+      hipLaunchKernelGGL(k_spike_corr, dim3(grid_for(ncols, kBlock)), dim3(kBlock), 0, st, W, ncols, n_moments, all_d,
+                         all_d + n_spikes, n_spikes, corr);
     // products: bins then points, each in column groups that fit a block
     // products: bin-edge columns then point columns, in groups that fit a block
-    auto apply = [&](const double* Wc, int cols, double* out) -> bool {
+    auto apply = [&](const double* Wc, const double* cc_corr, int cols, double* out) -> bool {
       const int per_grp = (4 * kBlock) / kRows;
       for (int c0 = 0; c0 < cols; c0 += per_grp) {
         const int cc = cols - c0 < per_grp ? cols - c0 : per_grp;
         hipLaunchKernelGGL(k_recon_apply, dim3(static_cast<unsigned>(ceil_div(n_rows, kRows))), dim3(kBlock), 0, st,
-                           mu, n_rows, n_moments, Wc + static_cast<int64_t>(c0) * n_moments, cc, out + c0, cols);
+                           mu, n_rows, n_moments, Wc + static_cast<int64_t>(c0) * n_moments, cc, out + c0, cols,
+                           cc_corr ? cc_corr + c0 : nullptr);
         if (hipGetLastError() != hipSuccess) return false;
       }
       return true;
     };
     bool ok = true;
-    if (nb) ok = apply(W, n_edges, F);
-    if (ok && np) ok = apply(W + static_cast<int64_t>(n_edges) * n_moments, np, rho);
+    if (nb) ok = apply(W, corr, n_edges, F);
+    if (ok && np) ok = apply(W + static_cast<int64_t>(n_edges) * n_moments, corr ? corr + n_edges : nullptr, np, rho);
     if (!ok) {
       set_error("nd_reconstruct: launch failed");
       s = ND_EDEVICE;
@@ -198,5 +233,7 @@ extern "C" nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_
   dfree(F);
   dfree(sb_d);
   dfree(sw_d);
+  dfree(corr);
+  dfree(all_d);
   return s;
 }
