@@ -89,6 +89,15 @@ __device__ inline void store16_nt(T* p, const T (&v)[16 / sizeof(T)]) {
   }
 }
 
+// Rademacher probe entry (j, node): the sign from the top bit of output
+// node+1 of probe j's SplitMix64 stream, which is seeded with output j+1 of
+// the stream seeded with `seed` (counter-based, so any row can be
+// regenerated in place).
+__device__ inline float rademacher_entry(uint64_t seed, int64_t j, int64_t node) {
+  const uint64_t key = splitmix64(seed, static_cast<uint64_t>(j) + 1);
+  return (splitmix64(key, static_cast<uint64_t>(node) + 1) >> 63) ? -1.0f : 1.0f;
+}
+
 // Neumaier-compensated accumulation.
 __device__ inline void neumaier(double& s, double& c, double x) {
   const double t = s + x;
@@ -111,6 +120,12 @@ struct StepArgs {
   const int32_t* chunk_owner;
   int64_t chunk_nnz;
   int64_t n_split;         // split rows are internal rows [0, n_split)
+  int slot_nnz;            // nonzeros per slot and gather batch (4 or 8)
+  int zmode;               // 0: probe rows read from z; 1: Rademacher rows regenerated
+  uint64_t seed;           // probe seed and index of this block's first probe (zmode 1)
+  int64_t j0;
+  const int32_t* zcls;     // zmode 1 with twin filtering: class of each internal row or -1
+  const void* zcls_val;    // [n_classes][kp] projected probe rows of the classes
   void* chunk_part;
   const void* xg;   // X_m, gathered
   void* xio;        // X_{m-1} in, X_{m+1} out
@@ -130,15 +145,15 @@ struct StepArgs {
 
 // Per-row epilogue: given Y_m(i, probes of this lane) in fp64 and the probe
 // values z, form the estimator terms v_ij = z_ij y_ij (+ g_im (1 - z_ij^2)
-// with a control variate), add them to this lane's per-probe sums, and write
+// with a control variate), add them to this lane's per-probe sums (kept in
+// LDS: mom[c * kBlock] for probe c of the lane), and write
 // the row's LDOS entry.  Called by every lane of the wavefront; `own` selects
 // the lanes that hold a row's values.  With `direct` set (rows split over
 // several wavefronts) the terms go to that row's own partial slot instead, so
 // the summation order does not depend on which wavefront finished the row.
 template <typename T, int L>
 __device__ inline void emit_moments(const StepArgs& a, bool own, int64_t node, const double (&y)[16 / sizeof(T)],
-                                    const T (&z)[16 / sizeof(T)], int q, double (&acc)[16 / sizeof(T)],
-                                    double* direct = nullptr) {
+                                    const T (&z)[16 / sizeof(T)], int q, double* mom, double* direct = nullptr) {
   constexpr int PPL = 16 / sizeof(T);
   double s1 = 0.0, s2 = 0.0;
   if (own) {
@@ -152,7 +167,7 @@ __device__ inline void emit_moments(const StepArgs& a, bool own, int64_t node, c
       if (direct)
         direct[q * PPL + c] = v;
       else
-        acc[c] += v;
+        mom[c * kBlock] += v;
       s1 += v;
       s2 += v * v;
     }
@@ -175,35 +190,65 @@ __device__ inline void emit_moments(const StepArgs& a, bool own, int64_t node, c
 }
 
 // The per-row operands that do not depend on the gathers: X_{m-1}(r), the
-// probe values and the node id.  Issued before the gathers so that their
-// latency overlaps with them.
-template <typename T>
+// node id and, when probe rows are read (ZM == 0), the probe values.  Issued
+// before the gathers so that their latency overlaps with them.
+template <typename T, int ZM>
 struct RowOperands {
   T xp[16 / sizeof(T)];
-  T z[16 / sizeof(T)];
+  T z[ZM == 0 ? 16 / sizeof(T) : 1];
   int64_t node;
 };
 
-template <typename T>
-__device__ inline void load_row_operands(const StepArgs& a, bool own, int64_t r, int q, RowOperands<T>& o) {
+template <typename T, int ZM>
+__device__ inline void load_row_operands(const StepArgs& a, bool own, int64_t r, int q, RowOperands<T, ZM>& o) {
   constexpr int PPL = 16 / sizeof(T);
   o.node = 0;
 #pragma unroll
-  for (int c = 0; c < PPL; ++c) o.xp[c] = o.z[c] = T(0);
+  for (int c = 0; c < PPL; ++c) o.xp[c] = T(0);
+  if constexpr (ZM == 0) {
+#pragma unroll
+    for (int c = 0; c < PPL; ++c) o.z[c] = T(0);
+  }
   if (own) {
     if (!a.first) load16_nt<T>(reinterpret_cast<const T*>(a.xio) + r * a.kp + q * PPL, o.xp);
-    load16_nt<T>(reinterpret_cast<const T*>(a.z) + r * a.kp + q * PPL, o.z);
-    if (a.ldos || a.cv_g) o.node = a.perm[r];
+    if (ZM == 1 || a.ldos || a.cv_g) o.node = a.perm[r];
+    if constexpr (ZM == 0) load16_nt<T>(reinterpret_cast<const T*>(a.z) + r * a.kp + q * PPL, o.z);
+  }
+}
+
+// Probe values of row r for this lane: read (ZM == 0), or regenerated from
+// the counter-based generator, twin-class rows taken from the class table.
+template <typename T, int ZM>
+__device__ inline void row_probes(const StepArgs& a, bool own, int64_t r, int q, const RowOperands<T, ZM>& o,
+                                  T (&z)[16 / sizeof(T)]) {
+  constexpr int PPL = 16 / sizeof(T);
+  if constexpr (ZM == 0) {
+#pragma unroll
+    for (int c = 0; c < PPL; ++c) z[c] = o.z[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < PPL; ++c) z[c] = T(0);
+    if (own) {
+      const int32_t cls = a.zcls ? a.zcls[r] : -1;
+      if (cls >= 0) {
+        load16<T>(reinterpret_cast<const T*>(a.zcls_val) + static_cast<int64_t>(cls) * a.kp + q * PPL, z);
+      } else {
+#pragma unroll
+        for (int c = 0; c < PPL; ++c) {
+          const int j = q * PPL + c;
+          if (j < a.k_batch) z[c] = static_cast<T>(rademacher_entry(a.seed, a.j0 + j, o.node));
+        }
+      }
+    }
   }
 }
 
 // Finish row r: X_{m+1} = 2/d * acc - X_{m-1} (or acc/d on the first step)
 // evaluated in the accumulator type A, stored in place, then the moment
 // epilogue on Y = sqrt(d) X.
-template <typename T, int L, typename A>
+template <typename T, int L, int ZM, typename A>
 __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_t d, const A (&acc)[16 / sizeof(T)],
-                                  const RowOperands<T>& o, int q, double (&mom)[16 / sizeof(T)],
-                                  double* direct = nullptr) {
+                                  const RowOperands<T, ZM>& o, int q, double* mom, double* direct = nullptr) {
   constexpr int PPL = 16 / sizeof(T);
   double y[PPL];
   if (own) {
@@ -226,68 +271,91 @@ __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_
 #pragma unroll
     for (int c = 0; c < PPL; ++c) y[c] = 0.0;
   }
-  emit_moments<T, L>(a, own, o.node, y, o.z, q, mom, direct);
+  T z[PPL];
+  row_probes<T, ZM>(a, own, r, q, o, z);
+  emit_moments<T, L>(a, own, o.node, y, z, q, mom, direct);
 }
 
-// Sum of X rows over the nonzeros e0+sub, e0+sub+P, ... < e1: four
-// independent gathers in flight per lane (predicated), added in a fixed order.
-template <typename T, int P>
+// Sum of X rows over the nonzeros e0+sub, e0+sub+P, ... < e1: U independent
+// gathers in flight per lane (predicated), added in a fixed order.
+template <typename T, int P, int U>
 __device__ inline void gather_sum(const StepArgs& a, int64_t e0, int64_t e1, int sub, int q,
                                   T (&acc)[16 / sizeof(T)]) {
   constexpr int PPL = 16 / sizeof(T);
-  const T* xg = reinterpret_cast<const T*>(a.xg);
+  const T* xg = reinterpret_cast<const T*>(a.xg) + q * PPL;
   const int64_t kp = a.kp;
-  for (int64_t e = e0 + sub; e < e1; e += 4 * P) {
-    int64_t j[4];
+  for (int64_t e = e0 + sub; e < e1; e += U * P) {
+    int32_t j[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      j[u] = (e + u * P < e1) ? static_cast<int64_t>(__builtin_nontemporal_load(a.col + e + u * P)) : -1;
-    T v[4][PPL];
+    for (int u = 0; u < U; ++u) {
+      const int64_t en = e + u * P;
+      j[u] = (en < e1) ? __builtin_nontemporal_load(a.col + en) : -1;
+    }
+    T v[U][PPL];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       if (j[u] >= 0) {
-        load16<T>(xg + j[u] * kp + q * PPL, v[u]);
+        load16<T>(xg + static_cast<int64_t>(j[u]) * kp, v[u]);
       } else {
 #pragma unroll
         for (int c = 0; c < PPL; ++c) v[u][c] = T(0);
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int c = 0; c < PPL; ++c) acc[c] += v[u][c];
   }
 }
 
-// Rows of one bin: P nonzero slots per row, 64/(P*L) consecutive rows per wavefront.
-template <typename T, int L, int P>
-__device__ inline void rows_item(const StepArgs& a, int bin, int64_t local_item, int lane,
-                                 double (&mom)[16 / sizeof(T)]) {
+// All items of one bin handled by this wavefront (items w, w+W, ...): P
+// nonzero slots per row, 64/(P*L) consecutive rows per item.  The row
+// pointers of item i+1 load while item i gathers.
+template <typename T, int L, int P, int U, int ZM>
+__device__ inline void rows_bin(const StepArgs& a, int bin, int64_t w, int64_t W, int lane, double* mom) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int G = P * L;
   constexpr int RPW = kWave / G;
   const int grp = lane / G, sub = (lane % G) / L, q = lane % L;
-  const int64_t r = a.bin_row_start[bin] + local_item * RPW + grp;
-  const bool active = r < a.bin_row_start[bin + 1];
-  const bool own = active && sub == 0;
-  const int64_t e0 = active ? a.row_ptr[r] : 0, e1 = active ? a.row_ptr[r + 1] : 0;
-  RowOperands<T> o;
-  load_row_operands<T>(a, own, r, q, o);
-  T acc[PPL];
+  const int64_t rs = a.bin_row_start[bin], re = a.bin_row_start[bin + 1];
+  const int64_t items = a.bin_item_start[bin + 1] - a.bin_item_start[bin];
+  if (w >= items) return;
+  auto rp = [&](int64_t li, int64_t& e0, int64_t& e1) {
+    const int64_t r = rs + li * RPW + grp;
+    if (li < items && r < re) {
+      e0 = a.row_ptr[r];
+      e1 = a.row_ptr[r + 1];
+    } else {
+      e0 = e1 = 0;
+    }
+  };
+  int64_t e0, e1;
+  rp(w, e0, e1);
+  for (int64_t li = w; li < items; li += W) {
+    const int64_t r = rs + li * RPW + grp;
+    const bool own = r < re && sub == 0;
+    RowOperands<T, ZM> o;
+    load_row_operands<T, ZM>(a, own, r, q, o);
+    int64_t e0n, e1n;
+    rp(li + W, e0n, e1n);
+    T acc[PPL];
 #pragma unroll
-  for (int c = 0; c < PPL; ++c) acc[c] = T(0);
-  gather_sum<T, P>(a, e0, e1, sub, q, acc);
+    for (int c = 0; c < PPL; ++c) acc[c] = T(0);
+    gather_sum<T, P, U>(a, e0, e1, sub, q, acc);
 #pragma unroll
-  for (int off = L; off < G; off <<= 1)
+    for (int off = L; off < G; off <<= 1)
 #pragma unroll
-    for (int c = 0; c < PPL; ++c) acc[c] += __shfl_xor(acc[c], off, kWave);
-  finish_row<T, L, T>(a, own, r, e1 - e0, acc, o, q, mom);
+      for (int c = 0; c < PPL; ++c) acc[c] += __shfl_xor(acc[c], off, kWave);
+    finish_row<T, L, ZM, T>(a, own, r, e1 - e0, acc, o, q, mom);
+    e0 = e0n;
+    e1 = e1n;
+  }
 }
 
 // One chunk of a split row: its partial sum (fp64) goes to the chunk's slot.
 // The rows are finished by k_split_finish after the step kernel, so no
 // device-wide fence is needed here.
-template <typename T, int L>
+template <typename T, int L, int U>
 __device__ inline void chunk_item(const StepArgs& a, int64_t c, int lane) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int P = kWave / L;
@@ -300,7 +368,7 @@ __device__ inline void chunk_item(const StepArgs& a, int64_t c, int lane) {
   T acc[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) acc[k] = T(0);
-  gather_sum<T, P>(a, e0, e1, sub, q, acc);
+  gather_sum<T, P, U>(a, e0, e1, sub, q, acc);
 #pragma unroll
   for (int off = L; off < kWave; off <<= 1)
 #pragma unroll
@@ -315,18 +383,17 @@ __device__ inline void chunk_item(const StepArgs& a, int64_t c, int lane) {
 // Split rows: one wavefront per row sums the row's chunk partials (slot s of
 // the wavefront takes chunks s, s+P, ... in order, then a fixed xor tree) and
 // finishes the row; the row's moment terms go to its own partial slot.
-template <typename T, int L>
+template <typename T, int L, int ZM>
 __global__ __launch_bounds__(kBlock) void k_split_finish(StepArgs a, int step_grid) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int P = kWave / L;
   const int lane = threadIdx.x & (kWave - 1), sub = lane / L, q = lane % L;
-  double unused[PPL];
   const double* part = reinterpret_cast<const double*>(a.chunk_part);
   for (int64_t r = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; r < a.n_split;
        r += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
     const int64_t c0 = a.split_chunk_ptr[r], c1 = a.split_chunk_ptr[r + 1];
-    RowOperands<T> o;
-    load_row_operands<T>(a, sub == 0, r, q, o);
+    RowOperands<T, ZM> o;
+    load_row_operands<T, ZM>(a, sub == 0, r, q, o);
     double tot[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) tot[k] = 0.0;
@@ -337,51 +404,47 @@ __global__ __launch_bounds__(kBlock) void k_split_finish(StepArgs a, int step_gr
     for (int off = L; off < kWave; off <<= 1)
 #pragma unroll
       for (int k = 0; k < PPL; ++k) tot[k] += __shfl_xor(tot[k], off, kWave);
-    finish_row<T, L, double>(a, sub == 0, r, a.row_ptr[r + 1] - a.row_ptr[r], tot, o, q, unused,
-                             a.partial + (static_cast<int64_t>(step_grid) + r) * a.kp);
+    finish_row<T, L, ZM, double>(a, sub == 0, r, a.row_ptr[r + 1] - a.row_ptr[r], tot, o, q, nullptr,
+                                 a.partial + (static_cast<int64_t>(step_grid) + r) * a.kp);
   }
 }
 
-// Block-level fixed-order reduction of the per-lane probe sums into
+// Block-level fixed-order reduction of the per-lane probe sums (LDS
+// s_mom[c][thread] for probe c of the thread's lane) into
 // partial[blockIdx.x][0..kp).
 template <typename T, int L>
-__device__ inline void block_partials(const StepArgs& a, const double (&mom)[16 / sizeof(T)]) {
+__device__ inline void block_partials(const StepArgs& a, const double (*s_mom)[kBlock]) {
   constexpr int PPL = 16 / sizeof(T);
-  __shared__ double red[kBlock][PPL];
-#pragma unroll
-  for (int c = 0; c < PPL; ++c) red[threadIdx.x][c] = mom[c];
   __syncthreads();
   if (static_cast<int>(threadIdx.x) < a.kp) {
     const int j = threadIdx.x, qq = j / PPL, cc = j % PPL;
     double s = 0.0, comp = 0.0;
-    for (int t = qq; t < kBlock; t += L) neumaier(s, comp, red[t][cc]);
+    for (int t = qq; t < kBlock; t += L) neumaier(s, comp, s_mom[cc][t]);
     a.partial[static_cast<int64_t>(blockIdx.x) * a.kp + j] = s + comp;
   }
 }
 
-template <typename T, int L>
+template <typename T, int L, int U, int ZM>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int PMAX = kWave / L;
-  const int lane = threadIdx.x & (kWave - 1);
-  double mom[PPL];
+  __shared__ double s_mom[PPL][kBlock];
 #pragma unroll
-  for (int c = 0; c < PPL; ++c) mom[c] = 0.0;
-  const int64_t n_waves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
-  for (int64_t it = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave; it < a.n_items;
-       it += n_waves) {
-    if (it < a.n_chunks) {
-      chunk_item<T, L>(a, it, lane);
-      continue;
-    }
-    const int64_t li = it - a.n_chunks;
-    int b = 0;
-    while (b + 1 < a.n_bins && li >= a.bin_item_start[b + 1]) ++b;
-    const int64_t bi = li - a.bin_item_start[b];
+  for (int c = 0; c < PPL; ++c) s_mom[c][threadIdx.x] = 0.0;
+  double* mom = &s_mom[0][threadIdx.x];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t W = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+  for (int64_t c = w; c < a.n_chunks; c += W) chunk_item<T, L, U>(a, c, lane);
+  // each bin continues the cyclic item order where the previous ones left
+  // off, so that the wavefronts stay evenly loaded
+  int64_t offset = a.n_chunks;
+  for (int b = 0; b < a.n_bins; ++b) {
+    const int64_t wb = ((w - offset) % W + W) % W;
     switch (a.bin_log2p[b]) {
 #define ND_BIN(B) \
   case B:         \
-    if constexpr ((1 << B) <= PMAX) rows_item<T, L, (1 << B)>(a, b, bi, lane, mom); \
+    if constexpr ((1 << B) <= PMAX) rows_bin<T, L, (1 << B), U, ZM>(a, b, wb, W, lane, mom); \
     break;
       ND_BIN(0)
       ND_BIN(1)
@@ -394,38 +457,42 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
       default:
         break;
     }
+    offset += a.bin_item_start[b + 1] - a.bin_item_start[b];
   }
-  block_partials<T, L>(a, mom);
+  block_partials<T, L>(a, s_mom);
 }
 
 // Moment 0: Y_0 = Z.  Internal rows in order, 64/L rows per wavefront.
-template <typename T, int L>
+template <typename T, int L, int ZM>
 __global__ __launch_bounds__(kBlock) void k_moment0(StepArgs a) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int RPW = kWave / L;
-  const int lane = threadIdx.x & (kWave - 1), q = lane % L, grp = lane / L;
-  double mom[PPL];
+  __shared__ double s_mom[PPL][kBlock];
 #pragma unroll
-  for (int c = 0; c < PPL; ++c) mom[c] = 0.0;
+  for (int c = 0; c < PPL; ++c) s_mom[c][threadIdx.x] = 0.0;
+  double* mom = &s_mom[0][threadIdx.x];
+  const int lane = threadIdx.x & (kWave - 1), q = lane % L, grp = lane / L;
   const int64_t n_waves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
   const int64_t items = ceil_div(a.n, RPW);
   for (int64_t it = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave; it < items;
        it += n_waves) {
     const int64_t r = it * RPW + grp;
     const bool own = r < a.n;
-    RowOperands<T> o;
-    load_row_operands<T>(a, own, r, q, o);
+    RowOperands<T, ZM> o;
+    load_row_operands<T, ZM>(a, own, r, q, o);
+    T z[PPL];
+    row_probes<T, ZM>(a, own, r, q, o, z);
     double y[PPL];
 #pragma unroll
-    for (int c = 0; c < PPL; ++c) y[c] = static_cast<double>(o.z[c]);
-    emit_moments<T, L>(a, own, o.node, y, o.z, q, mom);
+    for (int c = 0; c < PPL; ++c) y[c] = static_cast<double>(z[c]);
+    emit_moments<T, L>(a, own, o.node, y, z, q, mom);
   }
   // no split rows at moment 0: clear their slots
   double* sp = a.partial + static_cast<int64_t>(gridDim.x) * a.kp;
   for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < a.n_split * a.kp;
        t += static_cast<int64_t>(gridDim.x) * kBlock)
     sp[t] = 0.0;
-  block_partials<T, L>(a, mom);
+  block_partials<T, L>(a, s_mom);
 }
 
 }  // namespace
@@ -437,11 +504,8 @@ namespace {
 
 // Probe entry (j, i): see nd_make_probes in nd.h for the definition.
 __device__ inline float probe_value(uint64_t seed, int64_t j, int64_t i, bool gaussian) {
+  if (!gaussian) return rademacher_entry(seed, j, i);
   const uint64_t key = splitmix64(seed, static_cast<uint64_t>(j) + 1);
-  if (!gaussian) {
-    const uint64_t b = splitmix64(key, static_cast<uint64_t>(i) + 1);
-    return (b >> 63) ? -1.0f : 1.0f;
-  }
   const uint64_t b1 = splitmix64(key, 2 * static_cast<uint64_t>(i) + 1);
   const uint64_t b2 = splitmix64(key, 2 * static_cast<uint64_t>(i) + 2);
   const double u1 = (static_cast<double>(b1 >> 11) + 1.0) * 0x1.0p-53;
@@ -482,7 +546,7 @@ __global__ __launch_bounds__(kBlock) void k_project(const int64_t* __restrict__ 
                                                     const int32_t* __restrict__ members, int64_t n_classes,
                                                     int ld, int k_batch, const int64_t* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ inv, T* __restrict__ Z,
-                                                    T* __restrict__ X0) {
+                                                    T* __restrict__ X0, T* __restrict__ cmean) {
   const int64_t total = n_classes * k_batch;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; idx < total;
        idx += static_cast<int64_t>(gridDim.x) * kBlock) {
@@ -495,6 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_project(const int64_t* __restrict__ 
       s += static_cast<double>(Z[i * ld + j]);
     }
     const T mean = static_cast<T>(s / static_cast<double>(p1 - p0));
+    if (cmean) cmean[c * ld + j] = mean;
     for (int64_t p = p0; p < p1; ++p) {
       const int64_t i = inv ? static_cast<int64_t>(inv[members[p]]) : static_cast<int64_t>(members[p]);
       Z[i * ld + j] = mean;
@@ -504,6 +569,15 @@ __global__ __launch_bounds__(kBlock) void k_project(const int64_t* __restrict__ 
       }
     }
   }
+}
+
+// zcls[inv[i]] = class of member i (the array is -1 elsewhere).
+__global__ __launch_bounds__(kBlock) void k_zcls(const int64_t* __restrict__ class_ptr,
+                                                 const int32_t* __restrict__ members, int64_t n_classes,
+                                                 const int32_t* __restrict__ inv, int32_t* __restrict__ zcls) {
+  for (int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; c < n_classes;
+       c += static_cast<int64_t>(gridDim.x) * kBlock)
+    for (int64_t p = class_ptr[c]; p < class_ptr[c + 1]; ++p) zcls[inv[members[p]]] = static_cast<int32_t>(c);
 }
 
 // mu_pp[j0+j][m] = (1/N) sum over partial slots, for the `count` steps
@@ -570,6 +644,7 @@ int pow2_at_least(int x) {
 template <typename T, int L>
 int resident_grid() {
   static int grid = [] {
+    const auto kern = k_cheb_step<T, L, 8, 1>;
     if (const char* e = std::getenv("ND_STEP_GRID")) {
       const int v = std::atoi(e);
       if (v > 0) return v;
@@ -577,7 +652,7 @@ int resident_grid() {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cheb_step<T, L>, kBlock, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess ||
         cus <= 0 || per_cu <= 0) {
       (void)hipGetLastError();
       return 2048;
@@ -601,6 +676,16 @@ int step_grid(int L) {
     default: break;
   }
   return 2048;
+}
+
+// ND_PROBE_BUFFER=1 makes the step kernels read the probe block instead of
+// regenerating Rademacher rows (tuning experiments).
+bool probe_buffer_forced() {
+  static bool v = [] {
+    const char* e = std::getenv("ND_PROBE_BUFFER");
+    return e && std::atoi(e) == 1;
+  }();
+  return v;
 }
 
 // Probes per block of the recurrence (a power of two, at most 64);
@@ -631,20 +716,25 @@ struct MomentJob {
   bool timed = false;
 };
 
-template <typename T, int L>
-nd_status launch_step_kernels(const StepArgs& base, int grid, bool moment0, hipStream_t st) {
+template <typename T, int L, int ZM>
+nd_status launch_step_zm(const StepArgs& base, int grid, bool moment0, hipStream_t st) {
   if (moment0) {
-    hipLaunchKernelGGL((k_moment0<T, L>), dim3(grid), dim3(kBlock), 0, st, base);
+    hipLaunchKernelGGL((k_moment0<T, L, ZM>), dim3(grid), dim3(kBlock), 0, st, base);
   } else {
-    hipLaunchKernelGGL((k_cheb_step<T, L>), dim3(grid), dim3(kBlock), 0, st, base);
+    hipLaunchKernelGGL((k_cheb_step<T, L, 8, ZM>), dim3(grid), dim3(kBlock), 0, st, base);
     if (base.n_split > 0) {
       ND_LAUNCH_CHECK();
       const int g2 = grid_for(base.n_split, kWavesPerBlock, grid);
-      hipLaunchKernelGGL((k_split_finish<T, L>), dim3(g2), dim3(kBlock), 0, st, base, grid);
+      hipLaunchKernelGGL((k_split_finish<T, L, ZM>), dim3(g2), dim3(kBlock), 0, st, base, grid);
     }
   }
   ND_LAUNCH_CHECK();
   return ND_OK;
+}
+
+template <typename T, int L>
+nd_status launch_step_kernels(const StepArgs& base, int grid, bool moment0, hipStream_t st) {
+  return base.zmode ? launch_step_zm<T, L, 1>(base, grid, moment0, st) : launch_step_zm<T, L, 0>(base, grid, moment0, st);
 }
 
 template <typename T>
@@ -711,10 +801,27 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     hipLaunchKernelGGL(k_probes<T>, dim3(grid_for(N * kp, kBlock)), dim3(kBlock), 0, st, N, kp, kb,
                        static_cast<int64_t>(j0), job.seed, job.gaussian ? 1 : 0, in->row_ptr, in->perm, Z, A);
     ND_LAUNCH_CHECK();
-    if (job.motifs && job.motifs->n_classes > 0) {
+    // Rademacher rows are regenerated inside the step kernels (no probe-block
+    // reads); the projected rows of twin classes come from a small table
+    const int zmode = (!job.gaussian && !probe_buffer_forced()) ? 1 : 0;
+    const bool filt = job.motifs && job.motifs->n_classes > 0;
+    int32_t* zcls = nullptr;
+    T* zcls_val = nullptr;
+    if (filt) {
+      if (zmode) {
+        const size_t nc = static_cast<size_t>(job.motifs->n_classes);
+        ND_CHECK(g->ws_zcls.ensure(static_cast<size_t>(N) * 4 + 256 + nc * kp * sizeof(T)));
+        zcls = g->ws_zcls.as<int32_t>();
+        zcls_val = reinterpret_cast<T*>(reinterpret_cast<char*>(g->ws_zcls.p) + ((static_cast<size_t>(N) * 4 + 255) & ~size_t(255)));
+        ND_HIP(hipMemsetAsync(zcls, 0xFF, static_cast<size_t>(N) * 4, st));
+        ND_HIP(hipMemsetAsync(zcls_val, 0, nc * kp * sizeof(T), st));
+        hipLaunchKernelGGL(k_zcls, dim3(grid_for(job.motifs->n_classes, kBlock)), dim3(kBlock), 0, st,
+                           job.motifs->class_ptr, job.motifs->members, job.motifs->n_classes, in->inv, zcls);
+        ND_LAUNCH_CHECK();
+      }
       hipLaunchKernelGGL(k_project<T>, dim3(grid_for(job.motifs->n_classes * kb, kBlock)), dim3(kBlock), 0, st,
                          job.motifs->class_ptr, job.motifs->members, job.motifs->n_classes, kp, kb, in->row_ptr,
-                         in->inv, Z, A);
+                         in->inv, Z, A, zcls_val);
       ND_LAUNCH_CHECK();
     }
     StepArgs a{};
@@ -734,6 +841,12 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     a.chunk_owner = sc->chunk_owner;
     a.chunk_nnz = sc->chunk_nnz;
     a.n_split = sc->n_split;
+    a.slot_nnz = sc->slot_nnz;
+    a.zmode = zmode;
+    a.seed = job.seed;
+    a.j0 = j0;
+    a.zcls = zcls;
+    a.zcls_val = zcls_val;
     a.chunk_part = g->ws_chunk.p;
     a.z = Z;
     a.kp = kp;
@@ -842,11 +955,13 @@ nd_status nd_make_probes(const nd_graph* g, const nd_motifs* motifs, int32_t n_p
     if (flags & ND_STATE_FP64)
       hipLaunchKernelGGL(nd::k_project<double>, dim3(nd::grid_for(t2, nd::kBlock)), dim3(nd::kBlock), 0, st,
                          motifs->class_ptr, motifs->members, motifs->n_classes, n_probes, n_probes, g->row_ptr,
-                         static_cast<const int32_t*>(nullptr), static_cast<double*>(Z), static_cast<double*>(nullptr));
+                         static_cast<const int32_t*>(nullptr), static_cast<double*>(Z), static_cast<double*>(nullptr),
+                         static_cast<double*>(nullptr));
     else
       hipLaunchKernelGGL(nd::k_project<float>, dim3(nd::grid_for(t2, nd::kBlock)), dim3(nd::kBlock), 0, st,
                          motifs->class_ptr, motifs->members, motifs->n_classes, n_probes, n_probes, g->row_ptr,
-                         static_cast<const int32_t*>(nullptr), static_cast<float*>(Z), static_cast<float*>(nullptr));
+                         static_cast<const int32_t*>(nullptr), static_cast<float*>(Z), static_cast<float*>(nullptr),
+                         static_cast<float*>(nullptr));
     ND_LAUNCH_CHECK();
   }
   return ND_OK;

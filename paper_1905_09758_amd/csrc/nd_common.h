@@ -137,8 +137,9 @@ struct Internal {
 };
 
 // Row-to-wavefront mapping for a gathered row of L 16-byte lanes.  A row of
-// degree d gets P = 2^b nonzero slots, b = clamp(ceil(log2(ceil(d/4))), 0,
-// log2(64/L)), so one wavefront covers 64/(P*L) rows; rows longer than one
+// degree d gets P = 2^b nonzero slots, b = clamp(ceil(log2(ceil(d/S))), 0,
+// log2(64/L)) with S nonzeros per slot (the gathers one lane keeps in
+// flight), so one wavefront covers 64/(P*L) rows; rows longer than one
 // chunk (kChunkIters iterations of a full wavefront) are split into chunks
 // whose fp64 partial sums a second kernel combines in a fixed order.
 constexpr int kChunkIters = 32;
@@ -146,6 +147,7 @@ constexpr int kMaxBins = 8;
 
 struct Schedule {
   int L = 0;
+  int slot_nnz = 8;                    // nonzeros per slot: P = ceil(d / slot_nnz) (pow2)
   int n_bins = 0;                      // non-empty bins, in internal row order
   int bin_log2p[kMaxBins] = {0};
   int64_t bin_row_start[kMaxBins + 1] = {0};   // internal row ranges
@@ -170,7 +172,7 @@ struct nd_graph {
   float* dinv_sqrt = nullptr;  // [n]
   std::unique_ptr<nd::Internal> internal;              // built on first use
   std::map<int, std::unique_ptr<nd::Schedule>> sched;  // keyed by L
-  nd::Scratch ws_state, ws_partial, ws_chunk, ws_misc;  // moment workspaces
+  nd::Scratch ws_state, ws_partial, ws_chunk, ws_misc, ws_zcls;  // moment workspaces
   // ND_TIME_STEPS: HIP-event time of the sparse-product step launches of the
   // last moment call (the launches of moment 1 .. M-1 of every probe block)
   double step_ms = 0.0;

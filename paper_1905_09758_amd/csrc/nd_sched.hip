@@ -7,6 +7,8 @@
 // chunks come first, and the most-gathered rows -- the high-degree ones -- lie
 // next to each other, so their cache lines are shared by hot rows only.
 // Results do not depend on the numbering except through fp32 rounding order.
+#include <cstdlib>
+
 #include "nd_common.h"
 
 namespace nd {
@@ -67,7 +69,8 @@ __device__ inline int ceil_log2_dev(int64_t x) {
 
 // cnt[b] = rows with log2 P = b (b <= log2_pmax); cnt[log2_pmax + 1] = split rows.
 __global__ __launch_bounds__(kBlock) void k_bin_count(const int64_t* __restrict__ row_ptr, int64_t n, int log2_pmax,
-                                                      int64_t chunk_nnz, unsigned long long* __restrict__ cnt) {
+                                                      int64_t chunk_nnz, int slot_nnz,
+                                                      unsigned long long* __restrict__ cnt) {
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock; base < n;
        base += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int64_t i = base + threadIdx.x;
@@ -77,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int64_t* __restrict_
       if (d > chunk_nnz) {
         b = log2_pmax + 1;
       } else {
-        b = ceil_log2_dev((d + 3) / 4);
+        b = ceil_log2_dev((d + slot_nnz - 1) / slot_nnz);
         if (b > log2_pmax) b = log2_pmax;
       }
     }
@@ -171,7 +174,7 @@ nd_status get_schedule(nd_graph* g, int L, hipStream_t st, Schedule** out) {
     ND_CHECK(t.get(&dcnt, kMaxBins + 1));
     ND_HIP(hipMemsetAsync(dcnt, 0, sizeof(cnt), st));
     hipLaunchKernelGGL(k_bin_count, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, in->row_ptr, n, log2_pmax,
-                       s->chunk_nnz, dcnt);
+                       s->chunk_nnz, s->slot_nnz, dcnt);
     ND_LAUNCH_CHECK();
     ND_HIP(hipMemcpyAsync(cnt, dcnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
     ND_HIP(hipStreamSynchronize(st));
