@@ -229,8 +229,10 @@ nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_moments, ui
 nd_status nd_node_features(const nd_graph* g, const float* mean, const float* std, float* feat,
                            void* stream);
 
-/* Column sums over rows: out device double [2*ncol] = (sum x, sum x^2). */
-nd_status nd_column_stats(const float* x, int64_t n_rows, int32_t n_cols, double* out,
+/* Column statistics of x device float [n_rows][n_cols] (n_cols <= 16):
+ * mean[c] and std[c] = sqrt(max(E[x^2] - mean^2, 1e-12)) as device floats,
+ * from fp64 sums in a fixed order. */
+nd_status nd_column_stats(const float* x, int64_t n_rows, int32_t n_cols, float* mean, float* std,
                           void* stream);
 
 /* g device float [n][n_out] = MLP(params, feat [n][5]). */
@@ -247,7 +249,9 @@ nd_status nd_mlp_grad(const float* params, const float* feat, const float* targe
                       float* grad, float* loss, void* stream);
 
 /* One Adam step (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8, bias
- * correction with step count t >= 1) on device float arrays of n_params. */
+ * correction with step count t >= 1) on device float arrays of n_params.
+ * nd_mlp_grad and nd_adam_step keep a library-owned scratch buffer for the
+ * per-block gradient partials: calls must not overlap in time. */
 nd_status nd_adam_step(float* params, float* m, float* v, const float* grad, int64_t n_params,
                        int32_t t, float lr, void* stream);
 

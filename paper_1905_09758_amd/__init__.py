@@ -83,7 +83,7 @@ _sig("nd_last_error", [], ctypes.c_char_p)
 _HAS_CV = hasattr(_lib, "nd_node_features")
 if _HAS_CV:
     _sig("nd_node_features", [_vp, _vp, _vp, _vp, _vp])
-    _sig("nd_column_stats", [_vp, _i64, _i32, _vp, _vp])
+    _sig("nd_column_stats", [_vp, _i64, _i32, _vp, _vp, _vp])
     _sig("nd_mlp_forward", [_vp, _vp, _i64, _i32, _vp, _vp])
     _sig("nd_mlp_grad", [_vp, _vp, _vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp])
     _sig("nd_adam_step", [_vp, _vp, _vp, _vp, _i64, _i32, _flt, _vp])
@@ -304,11 +304,12 @@ def nd_node_features(g: Graph, feat, mean=None, std=None, stream=None):
                                  _stream(stream)), "nd_node_features")
 
 
-def nd_column_stats(x, n_rows: int, n_cols: int, out, stream=None):
+def nd_column_stats(x, n_rows: int, n_cols: int, mean, std, stream=None):
     import torch
     _need_cv()
     _check(_lib.nd_column_stats(_dev(x, torch.float32, n_rows * n_cols, "x"), n_rows, n_cols,
-                                _dev(out, torch.float64, 2 * n_cols, "out"), _stream(stream)), "nd_column_stats")
+                                _dev(mean, torch.float32, n_cols, "mean"), _dev(std, torch.float32, n_cols, "std"),
+                                _stream(stream)), "nd_column_stats")
 
 
 def nd_mlp_forward(params, feat, n: int, n_out: int, g, stream=None):

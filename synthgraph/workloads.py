@@ -52,3 +52,45 @@ WORKLOADS = {
     "rmat22": Workload("rmat22", 32, 1000, 200, False, False,
                        "R-MAT scale 22 ef 16, 32 Rademacher probes, 1000 moments, global DOS"),
 }
+
+
+# ---------------------------------------------------------------- control-variate graphs
+# Families and parameters of the learned-control-variate study: Erdos-Renyi
+# with mean degree U[4, 20]; Barabasi-Albert with m in {2..6}; R-MAT with
+# edge factor 8 or 16 at scale ceil(log2 n), endpoints reduced mod n; a
+# 4-block SBM with p_in = 0.01, p_out = 0.001.  n is uniform in [n_lo, n_hi].
+CV_FAMILIES = ("er", "ba", "rmat", "sbm")
+
+
+def cv_graph_specs(count: int, seed: int, n_lo: int = 10_000, n_hi: int = 200_000):
+    """`count` (family, n, parameter, graph seed) tuples, families in turn."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        fam = CV_FAMILIES[i % len(CV_FAMILIES)]
+        n = int(rng.integers(n_lo, n_hi + 1))
+        if fam == "er":
+            par = float(rng.uniform(4.0, 20.0))
+        elif fam == "ba":
+            par = int(rng.integers(2, 7))
+        elif fam == "rmat":
+            par = int(rng.choice([8, 16]))
+        else:
+            par = 0
+        specs.append((fam, n, par, int(rng.integers(1, 2**31 - 1))))
+    return specs
+
+
+def cv_graph(spec):
+    fam, n, par, gseed = spec
+    if fam == "er":
+        return sg.erdos_renyi(n, par / (n - 1), seed=gseed)
+    if fam == "ba":
+        return sg.barabasi_albert(n, par, seed=gseed)
+    if fam == "rmat":
+        scale = max(1, (n - 1).bit_length())
+        return sg.rmat(scale, par, seed=gseed, n_mod=n)
+    if fam == "sbm":
+        return sg.sbm(n, 0.01, 0.001, seed=gseed)
+    raise ValueError(fam)

@@ -1,0 +1,153 @@
+"""Learned control variate on the GPU vs the fp64 oracle (needs an MI355X).
+
+The control variate is not in the paper: features, MLP and Adam are pinned to
+their definitions (parity unpinned by the paper); the estimator's variance is
+pinned to the closed form of the oracle."""
+import numpy as np
+import pytest
+
+import synthgraph as sg
+from synthgraph.mlp_init import init_params
+from synthgraph import workloads
+from oracle import graph as og
+from oracle import cv as ocv
+from oracle import kpm
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x, dtype):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+GRAPHS = {
+    "er": lambda: sg.erdos_renyi(600, 0.02, seed=3),
+    "ba_twins": lambda: sg.barabasi_albert(900, 3, seed=2, twin_pairs=40),
+    "rmat": lambda: sg.rmat(10, 8, seed=5),
+    "star": lambda: sg.star(700),
+    "sbm": lambda: sg.sbm(1200, 0.05, 0.005, seed=1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+def test_features(nd, name):
+    import torch
+    n, s, d = GRAPHS[name]()
+    g = nd.nd_build_csr(n, s, d)
+    want = ocv.log_scale(ocv.raw_features(og.build_csr(n, s, d)))
+    f = torch.empty(g.n * 5, dtype=torch.float32, device="cuda")
+    nd.nd_node_features(g, f)
+    got = f.cpu().numpy().reshape(g.n, 5)
+    assert np.allclose(got, want, rtol=1e-6, atol=1e-6)
+    mean = want.mean(axis=0).astype(np.float32)
+    std = (want.std(axis=0) + 0.5).astype(np.float32)
+    nd.nd_node_features(g, f, _t(mean, torch.float32), _t(std, torch.float32))
+    got2 = f.cpu().numpy().reshape(g.n, 5)
+    assert np.allclose(got2, (want - mean) / std, rtol=1e-5, atol=1e-5)
+
+
+def test_column_stats(nd):
+    import torch
+    x = np.random.default_rng(0).normal(3.0, 2.0, size=(100_003, 5)).astype(np.float32)
+    mean = torch.empty(5, dtype=torch.float32, device="cuda")
+    std = torch.empty(5, dtype=torch.float32, device="cuda")
+    nd.nd_column_stats(_t(x, torch.float32), x.shape[0], 5, mean, std)
+    x64 = x.astype(np.float64)
+    assert np.allclose(mean.cpu().numpy(), x64.mean(axis=0), rtol=1e-6)
+    assert np.allclose(std.cpu().numpy(), x64.std(axis=0), rtol=1e-5)
+
+
+@pytest.mark.parametrize("n,n_out", [(1, 64), (97, 64), (1000, 7), (333, 128)])
+def test_mlp_forward(nd, n, n_out):
+    import torch
+    p = init_params(11, n_out)
+    x = np.random.default_rng(n).normal(size=(n, 5)).astype(np.float32)
+    out = torch.empty(n * n_out, dtype=torch.float32, device="cuda")
+    nd.nd_mlp_forward(_t(p, torch.float32), _t(x, torch.float32), n, n_out, out)
+    want = ocv.forward(p.astype(np.float64), x.astype(np.float64), n_out)
+    got = out.cpu().numpy().reshape(n, n_out)
+    assert np.max(np.abs(got - want)) <= 1e-4 * (1.0 + np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("n,n_out,use_idx", [(64, 64, False), (4096, 64, True), (77, 13, True)])
+def test_mlp_grad(nd, n, n_out, use_idx):
+    import torch
+    rng = np.random.default_rng(n + n_out)
+    p = init_params(5, n_out).astype(np.float32)
+    p[-n_out:] = rng.normal(size=n_out).astype(np.float32) * 0.1
+    rows = 2 * n + 5
+    x = rng.normal(size=(rows, 5)).astype(np.float32)
+    y = rng.normal(size=(rows, n_out + 3)).astype(np.float32)  # ld_target > n_out
+    idx = rng.integers(0, rows, size=n).astype(np.int32) if use_idx else np.arange(n, dtype=np.int32)
+    grad = torch.empty(nd.n_params(n_out), dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    nd.nd_mlp_grad(_t(p, torch.float32), _t(x, torch.float32), _t(y, torch.float32), n_out + 3,
+                   _t(idx, torch.int32) if use_idx else None, n, n_out, grad, loss)
+    l_o, g_o = ocv.mse_grad(p.astype(np.float64), x[idx].astype(np.float64),
+                            y[idx, :n_out].astype(np.float64), n_out)
+    g = grad.cpu().numpy()
+    assert abs(loss.item() - l_o) <= 1e-5 * abs(l_o)
+    assert np.max(np.abs(g - g_o)) <= 1e-3 * np.max(np.abs(g_o)) + 1e-6
+
+
+def test_adam(nd):
+    import torch
+    rng = np.random.default_rng(1)
+    P = 1000
+    p, m, v, g = (rng.normal(size=P).astype(np.float32) for _ in range(4))
+    v = np.abs(v)
+    dp, dm, dv = _t(p, torch.float32), _t(m, torch.float32), _t(v, torch.float32)
+    for t in (1, 2, 3):
+        nd.nd_adam_step(dp, dm, dv, _t(g, torch.float32), P, t, 1e-3)
+        p, m, v = ocv.adam_step(p.astype(np.float64), m.astype(np.float64), v.astype(np.float64), g, t, 1e-3)
+    assert np.allclose(dp.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+    assert np.allclose(dv.cpu().numpy(), v, rtol=1e-5, atol=1e-9)
+
+
+def test_cv_variance_matches_closed_form(nd):
+    """Per-probe variance of the Gaussian estimator with a fixed control
+    variate g equals V_R + 2 (b - g)^2 (oracle, from exact PDOS moments)."""
+    import torch
+    n, s, d = sg.erdos_renyi(400, 0.03, seed=9)
+    g_or = og.build_csr(n, s, d)
+    M = 8
+    _, l_x = kpm.exact_moments_eig(og.normalized_adjacency(g_or), 2 * M)
+    G = (l_x[:, :M] + 0.2 * np.random.default_rng(0).normal(size=(g_or.n, M))).astype(np.float32)
+    g = nd.nd_build_csr(n, s, d)
+    k = 4000
+    ld = torch.empty(g.n * M, dtype=torch.float64, device="cuda")
+    sq = torch.empty(g.n * M, dtype=torch.float64, device="cuda")
+    nd.nd_ldos_moments(g, None, k, M, 3, nd.ND_PROBE_GAUSSIAN, ld, cv_g=_t(G, torch.float32), ldos_sq=sq)
+    s2 = ((sq - ld * ld) * (k / (k - 1.0))).cpu().numpy().reshape(g.n, M)
+    want = kpm.ldos_probe_variance(l_x, M, "gaussian", G.astype(np.float64))
+    # sample variances of 4000 probes: ~ sqrt(2/k) relative error per entry; compare averages
+    assert np.allclose(s2[:, 1:].mean(axis=0), want[:, 1:].mean(axis=0), rtol=0.05, atol=1e-3)
+    # unbiased: the estimate agrees with the exact PDOS moments
+    C = ld.cpu().numpy().reshape(g.n, M)
+    assert np.max(np.abs(C.mean(axis=0) - l_x[:, :M].mean(axis=0))) < 0.02
+
+
+def test_training_reduces_gaussian_variance(nd):
+    """Train on a few small graphs of the study's families, then the learned
+    control variate lowers the Gaussian per-probe variance on held-out
+    graphs; with +/-1 probes it changes nothing (the estimator is identical)."""
+    import torch
+    from paper_1905_09758_amd import cv
+    M = 16
+    specs = workloads.cv_graph_specs(8, seed=1, n_lo=2000, n_hi=6000)
+    held = workloads.cv_graph_specs(2, seed=99, n_lo=2000, n_hi=6000)
+    graphs = [nd.nd_build_csr(*workloads.cv_graph(sp)) for sp in specs]
+    targets = [cv.ldos_targets(g, 256, M, seed=5 + i) for i, g in enumerate(graphs)]
+    model, hist = cv.train(graphs, targets, M, init_params(0, M), steps=600, batch=2048, lr=3e-3, seed=0,
+                           log_every=100)
+    assert hist[-1][1] < hist[0][1]
+    for sp in held:
+        g = nd.nd_build_csr(*workloads.cv_graph(sp))
+        gcv = cv.predict(g, model)
+        v_plain = cv.probe_variance(g, M, 512, 7, gaussian=True)
+        v_cv = cv.probe_variance(g, M, 512, 7, gaussian=True, cv_g=gcv)
+        assert v_cv < 0.9 * v_plain, (sp, v_plain, v_cv)
+        r_plain = cv.probe_variance(g, M, 128, 8, gaussian=False)
+        r_cv = cv.probe_variance(g, M, 128, 8, gaussian=False, cv_g=gcv)
+        assert abs(r_cv - r_plain) <= 1e-6 * r_plain
