@@ -24,6 +24,7 @@ bounded sample, following the paper's timing protocol (the first 10 moments).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -45,6 +46,38 @@ def algorithmic_bytes(n: int, nnz: int, k: int, ldos: bool, state_bytes: int = 4
     if ldos:
         b += 8 * n
     return b
+
+
+# Sources the sparse step kernel is compiled from; a counter record applies
+# only to the build of these exact files.
+STEP_KERNEL_SOURCES = ("nd_common.h", "nd_sched.hip", "nd_cheb.hip")
+
+
+def step_kernel_sha256() -> str:
+    h = hashlib.sha256()
+    for f in STEP_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1905_09758_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per launch of the step kernel for `workload`, from the
+    committed counter summary (FETCH_SIZE and WRITE_SIZE runs scaled by a
+    plain copy), or None when there is none or it was taken on other kernel
+    sources."""
+    path = os.path.join(ROOT, "profiles", f"k_cheb_step_{workload}.md")
+    try:
+        with open(path) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        if line.startswith("traffic_record: "):
+            rec = json.loads(line[len("traffic_record: "):])
+            if rec.get("kernel_sources_sha256") == step_kernel_sha256():
+                return int(rec["bytes_per_launch"])
+    return None
 
 
 def cpu_model() -> str:
@@ -83,12 +116,107 @@ def cpu_baseline(workload: str, k: int, ldos: bool, seed: int):
             "sample": sample + "; fp64 numpy/scipy single thread, %.2f s, host CPU: %s" % (dt, cpu_model())}
 
 
+def cv_study(args) -> dict:
+    """Learned control variate (config 5): train on synthetic graphs of four
+    families with LDOS targets from the method itself, then compare the
+    probes needed for a per-node, per-moment variance of 1e-3 on held-out
+    graphs: plain Rademacher, plain Gaussian, Gaussian with the learned
+    diagonal control variate."""
+    import torch
+    import paper_1905_09758_amd as nd
+    from paper_1905_09758_amd import cv
+    from synthgraph import workloads
+    from synthgraph.mlp_init import init_params
+    M = 64
+    t0 = time.perf_counter()
+    train_specs = workloads.cv_graph_specs(args.cv_train, 101, args.cv_nmin, args.cv_nmax)
+    held_specs = workloads.cv_graph_specs(args.cv_held, 202, args.cv_nmin, args.cv_nmax)
+    graphs, targets, t_gen, t_tgt = [], [], 0.0, 0.0
+    for i, sp in enumerate(train_specs):
+        a = time.perf_counter()
+        n, s, d = workloads.cv_graph(sp)
+        b = time.perf_counter()
+        g = nd.nd_build_csr(n, s, d)
+        targets.append(cv.ldos_targets(g, args.cv_target_probes, M, seed=1000 + i))
+        graphs.append(g)
+        torch.cuda.synchronize()
+        t_gen += b - a
+        t_tgt += time.perf_counter() - b
+        if (i + 1) % 20 == 0:
+            print("cv5: %d/%d training graphs (gen %.0f s, build+targets %.0f s)" % (i + 1, len(train_specs), t_gen, t_tgt),
+                  file=sys.stderr, flush=True)
+    nodes = sum(g.n for g in graphs)
+    a = time.perf_counter()
+    model, hist = cv.train(graphs, targets, M, init_params(0, M), steps=args.cv_steps, batch=4096, lr=2e-3,
+                           seed=0, log_every=max(1, args.cv_steps // 10))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - a
+    del targets
+    rows = []
+    for j, sp in enumerate(held_specs):
+        n, s, d = workloads.cv_graph(sp)
+        g = nd.nd_build_csr(n, s, d)
+        gcv = cv.predict(g, model)
+        row = {"family": sp[0], "n": g.n, "nnz": g.nnz}
+        seed = 5000 + 17 * j
+        row["v_rademacher"] = cv.probe_variance(g, M, 256, seed, gaussian=False)
+        row["v_gaussian"] = cv.probe_variance(g, M, 256, seed + 1, gaussian=True)
+        row["v_gaussian_cv"] = cv.probe_variance(g, M, 256, seed + 2, gaussian=True, cv_g=gcv)
+        if j < 4:  # empirical check of the k-probe variance on the first held-out graphs
+            emp = {}
+            for k in (4, 8, 16, 32):
+                emp[str(k)] = {
+                    "gaussian": cv.empirical_variance(g, M, k, 16, seed + 100 + k, True) * k,
+                    "gaussian_cv": cv.empirical_variance(g, M, k, 16, seed + 200 + k, True, cv_g=gcv) * k,
+                    "rademacher": cv.empirical_variance(g, M, k, 16, seed + 300 + k, False) * k,
+                }
+            row["k_times_var_of_k_probe_mean"] = emp
+        rows.append(row)
+        del g, gcv
+    target = 1e-3
+    probes = {arm: float(np.mean([r["v_" + arm] for r in rows])) / target
+              for arm in ("rademacher", "gaussian", "gaussian_cv")}
+    by_family = {}
+    for fam in sorted(set(r["family"] for r in rows)):
+        rs = [r for r in rows if r["family"] == fam]
+        by_family[fam] = {arm: round(float(np.mean([r["v_" + arm] for r in rs])) / target, 1)
+                          for arm in ("rademacher", "gaussian", "gaussian_cv")}
+    return {
+        "metric": METRIC,
+        "value": round(probes["gaussian_cv"], 1),
+        "unit": "probes to 1e-3 LDOS variance (learned CV, Gaussian probes)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cv5", "train_graphs": len(train_specs), "train_nodes": nodes,
+                   "held_out_graphs": len(held_specs), "n_range": [args.cv_nmin, args.cv_nmax],
+                   "target_probes": args.cv_target_probes, "moments": M, "mlp": "5-128-128-64 relu",
+                   "train_steps": args.cv_steps, "batch": 4096},
+        "probes_to_1e-3": {k: round(v, 1) for k, v in probes.items()},
+        "probes_saved_vs_gaussian": round(1.0 - probes["gaussian_cv"] / probes["gaussian"], 4),
+        "probes_saved_vs_rademacher": round(1.0 - probes["gaussian_cv"] / probes["rademacher"], 4),
+        "by_family": by_family,
+        "held_out": rows,
+        "train_loss": hist,
+        "seconds": {"generate": round(t_gen, 1), "build_and_targets": round(t_tgt, 1),
+                    "train": round(t_train, 1), "total": round(time.perf_counter() - t0, 1)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ba1m_twins", choices=["ba1m_twins", "rmat27", "rmat22", "er2000"])
+    ap.add_argument("--workload", default="ba1m_twins", choices=["ba1m_twins", "rmat27", "rmat22", "er2000", "cv5"])
+    ap.add_argument("--cv-train", type=int, default=200, help="cv5: training graphs")
+    ap.add_argument("--cv-held", type=int, default=20, help="cv5: held-out graphs")
+    ap.add_argument("--cv-nmin", type=int, default=10_000)
+    ap.add_argument("--cv-nmax", type=int, default=200_000)
+    ap.add_argument("--cv-target-probes", type=int, default=1024)
+    ap.add_argument("--cv-steps", type=int, default=3000)
     ap.add_argument("--no-filter", action="store_true", help="skip twin filtering (ba1m_twins)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
@@ -112,6 +240,9 @@ def main():
     import paper_1905_09758_amd as nd
     from synthgraph.workloads import WORKLOADS
     nd.require_gpu()
+    if args.workload == "cv5":
+        print(json.dumps(cv_study(args)), flush=True)
+        return
     W = WORKLOADS[args.workload]
     k, M = W.probes, W.moments
     use_filter = W.filter_twins and not args.no_filter
@@ -172,6 +303,7 @@ def main():
     avg_launch_ms = kern_ms / max(kern_n, 1)
     b_launch = algorithmic_bytes(n, nnz, k, W.ldos)
     achieved = b_launch / (avg_launch_ms * 1e-3) / 1e9
+    traffic = profiled_traffic(args.workload)
     mu = out["mu"].cpu().numpy()
     line = {
         "metric": METRIC,
@@ -190,7 +322,8 @@ def main():
                    "probes": k, "moments": M, "twin_filter": use_filter, "twin_classes": n_cls,
                    "ldos": W.ldos, "state": "fp32 recurrence, fp64 compensated moment sums"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
                      "kernel": "k_cheb_step", "avg_launch_ms": round(avg_launch_ms, 5),
                      "algorithmic_bytes_per_launch": b_launch},
         "spmm_only_G_per_s": round(work / (kern_ms * 1e-3 / args.steps) / 1e9, 3) if kern_ms else None,

@@ -207,7 +207,15 @@ nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
  *           [e_b, e_{b+1}) except the last, plus point masses spike_weight[s]
  *           at spike_lambda[s] (host arrays of n_spikes entries, may be 0);
  *   rho     device double [n_rows][n_points] or NULL: rho at the Chebyshev
- *           nodes x_k = cos(pi (k + 1/2) / n_points), k = 0..n_points-1. */
+ *           nodes x_k = cos(pi (k + 1/2) / n_points), k = 0..n_points-1.
+ * With ND_SPIKES_IN_MOMENTS in `kernel`, the rows hold the moments of the
+ * point masses too: sum_s spike_weight[s] T_m(spike_lambda[s]) is taken out
+ * before the series, so hist is the smooth part's plus the exact masses and
+ * rho is the smooth part's density.
+ * Errors: ND_EINVAL for null pointers or sizes outside the ranges above
+ * (n_bins, n_points in 1..4096, n_spikes in 0..64); ND_ENOMEM / ND_EDEVICE
+ * from the device.  The call synchronises the stream before it returns
+ * (it releases its temporary tables). */
 nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_moments, uint32_t kernel,
                          const double* spike_lambda, const double* spike_weight, int32_t n_spikes,
                          int32_t n_bins, double lo, double hi, double* hist, int32_t n_points,

@@ -76,19 +76,35 @@ def normalized_adjacency(g: Graph) -> sp.csr_matrix:
 
 
 def neighbor_sets_from_edges(src, dst, nodes) -> dict:
-    """N(v) for each original id v in `nodes`, read straight from an edge list
-    (symmetrised, deduplicated, self-loops dropped).  Used for sampled checks on
-    graphs too large to build in full here."""
+    """N(v) (sorted array of input ids) for each input id v in `nodes`, read
+    straight from an edge list (symmetrised, deduplicated, self-loops
+    dropped).  Used for sampled checks on graphs too large to build here."""
     src = np.asarray(src)
     dst = np.asarray(dst)
     nodes = np.unique(np.asarray(nodes, dtype=np.int64))
-    out = {int(v): set() for v in nodes}
-    m1 = np.isin(src, nodes)
-    for a, b in zip(src[m1].tolist(), dst[m1].tolist()):
-        if a != b:
-            out[a].add(b)
-    m2 = np.isin(dst, nodes)
-    for a, b in zip(dst[m2].tolist(), src[m2].tolist()):
-        if a != b:
-            out[a].add(b)
-    return out
+    m1 = np.isin(src, nodes, kind="table")
+    m2 = np.isin(dst, nodes, kind="table")
+    a = np.concatenate([src[m1], dst[m2]]).astype(np.int64)
+    b = np.concatenate([dst[m1], src[m2]]).astype(np.int64)
+    keep = a != b
+    a, b = a[keep], b[keep]
+    base = np.int64(max(int(src.max(initial=0)), int(dst.max(initial=0))) + 1)
+    key = np.unique(a * base + b)
+    a, b = key // base, key % base
+    starts = np.searchsorted(a, nodes, side="left")
+    ends = np.searchsorted(a, nodes, side="right")
+    return {int(v): b[s0:s1] for v, s0, s1 in zip(nodes, starts, ends)}
+
+
+def compact_ids_from_edges(n_nodes: int, src, dst) -> np.ndarray:
+    """Compact id of every input id (-1 for isolated ones): the rank among the
+    ids that have at least one non-loop edge (ascending), as in build_csr."""
+    src = np.asarray(src)
+    dst = np.asarray(dst)
+    keep = src != dst
+    present = np.zeros(n_nodes, dtype=bool)
+    present[src[keep]] = True
+    present[dst[keep]] = True
+    cid = np.cumsum(present, dtype=np.int64) - 1
+    cid[~present] = -1
+    return cid

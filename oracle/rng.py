@@ -79,3 +79,14 @@ def probes(n_nodes: int, n_probes: int, seed: int, kind: str = "rademacher") -> 
     if kind == "gaussian":
         return gaussian(n_nodes, n_probes, seed)
     raise ValueError(kind)
+
+
+def rademacher_at(nodes: np.ndarray, n_probes: int, seed: int) -> np.ndarray:
+    """Rows `nodes` of the Rademacher probe block: [len(nodes)][n_probes]
+    (same definition as :func:`rademacher`, evaluated at selected node ids)."""
+    idx = np.asarray(nodes, dtype=np.uint64) + np.uint64(1)
+    Z = np.empty((idx.size, n_probes), np.float64)
+    for j in range(n_probes):
+        b = splitmix64_np(probe_key(seed, j), idx)
+        Z[:, j] = np.where((b >> np.uint64(63)) != 0, -1.0, 1.0)
+    return Z

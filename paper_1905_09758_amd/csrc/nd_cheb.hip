@@ -135,7 +135,8 @@ struct StepArgs {
   int k_batch;      // real probes in this block
   double inv_k;     // 1 / (total probe count over all blocks)
   int m;            // moment index written by this launch
-  double* partial;  // [gridDim.x + n_split][kp] per-probe partial sums for moment m
+  double* partial;  // [step grid + split_blocks][kp] per-probe partial sums for moment m
+  int split_blocks; // grid of the split-row finisher; its slots follow the step kernel's
   double* ldos;     // [n][ld] (compact node order) or null
   double* ldos_sq;  // [n][ld] or null
   int64_t ld;       // leading dimension of ldos / cv_g (= number of moments)
@@ -148,12 +149,10 @@ struct StepArgs {
 // with a control variate), add them to this lane's per-probe sums (kept in
 // LDS: mom[c * kBlock] for probe c of the lane), and write
 // the row's LDOS entry.  Called by every lane of the wavefront; `own` selects
-// the lanes that hold a row's values.  With `direct` set (rows split over
-// several wavefronts) the terms go to that row's own partial slot instead, so
-// the summation order does not depend on which wavefront finished the row.
+// the lanes that hold a row's values.
 template <typename T, int L>
 __device__ inline void emit_moments(const StepArgs& a, bool own, int64_t node, const double (&y)[16 / sizeof(T)],
-                                    const T (&z)[16 / sizeof(T)], int q, double* mom, double* direct = nullptr) {
+                                    const T (&z)[16 / sizeof(T)], int q, double* mom) {
   constexpr int PPL = 16 / sizeof(T);
   double s1 = 0.0, s2 = 0.0;
   if (own) {
@@ -164,10 +163,7 @@ __device__ inline void emit_moments(const StepArgs& a, bool own, int64_t node, c
       double v = zc * y[c];
       if (a.cv_g) v += g * (1.0 - zc * zc);
       if (q * PPL + c >= a.k_batch) v = 0.0;
-      if (direct)
-        direct[q * PPL + c] = v;
-      else
-        mom[c * kBlock] += v;
+      mom[c * kBlock] += v;
       s1 += v;
       s2 += v * v;
     }
@@ -248,7 +244,7 @@ __device__ inline void row_probes(const StepArgs& a, bool own, int64_t r, int q,
 // epilogue on Y = sqrt(d) X.
 template <typename T, int L, int ZM, typename A>
 __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_t d, const A (&acc)[16 / sizeof(T)],
-                                  const RowOperands<T, ZM>& o, int q, double* mom, double* direct = nullptr) {
+                                  const RowOperands<T, ZM>& o, int q, double* mom) {
   constexpr int PPL = 16 / sizeof(T);
   double y[PPL];
   if (own) {
@@ -273,7 +269,7 @@ __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_
   }
   T z[PPL];
   row_probes<T, ZM>(a, own, r, q, o, z);
-  emit_moments<T, L>(a, own, o.node, y, z, q, mom, direct);
+  emit_moments<T, L>(a, own, o.node, y, z, q, mom);
 }
 
 // Sum of X rows over the nonzeros e0+sub, e0+sub+P, ... < e1: U independent
@@ -380,13 +376,35 @@ __device__ inline void chunk_item(const StepArgs& a, int64_t c, int lane) {
   }
 }
 
+// Block-level fixed-order reduction of the per-lane probe sums (LDS
+// s_mom[c][thread] for probe c of the thread's lane) into
+// partial[blockIdx.x][0..kp).
+template <typename T, int L>
+__device__ inline void block_partials(const StepArgs& a, const double (*s_mom)[kBlock]) {
+  constexpr int PPL = 16 / sizeof(T);
+  __syncthreads();
+  if (static_cast<int>(threadIdx.x) < a.kp) {
+    const int j = threadIdx.x, qq = j / PPL, cc = j % PPL;
+    double s = 0.0, comp = 0.0;
+    for (int t = qq; t < kBlock; t += L) neumaier(s, comp, s_mom[cc][t]);
+    a.partial[static_cast<int64_t>(blockIdx.x) * a.kp + j] = s + comp;
+  }
+}
+
 // Split rows: one wavefront per row sums the row's chunk partials (slot s of
 // the wavefront takes chunks s, s+P, ... in order, then a fixed xor tree) and
-// finishes the row; the row's moment terms go to its own partial slot.
+// finishes the row.  Rows go to wavefronts in a fixed cyclic order and the
+// moment terms are reduced per block like the step kernel's, into the slots
+// after the step kernel's (the grid depends only on the graph, so the sums
+// are reproducible).
 template <typename T, int L, int ZM>
 __global__ __launch_bounds__(kBlock) void k_split_finish(StepArgs a, int step_grid) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int P = kWave / L;
+  __shared__ double s_mom[PPL][kBlock];
+#pragma unroll
+  for (int c = 0; c < PPL; ++c) s_mom[c][threadIdx.x] = 0.0;
+  double* mom = &s_mom[0][threadIdx.x];
   const int lane = threadIdx.x & (kWave - 1), sub = lane / L, q = lane % L;
   const double* part = reinterpret_cast<const double*>(a.chunk_part);
   for (int64_t r = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; r < a.n_split;
@@ -404,24 +422,11 @@ __global__ __launch_bounds__(kBlock) void k_split_finish(StepArgs a, int step_gr
     for (int off = L; off < kWave; off <<= 1)
 #pragma unroll
       for (int k = 0; k < PPL; ++k) tot[k] += __shfl_xor(tot[k], off, kWave);
-    finish_row<T, L, ZM, double>(a, sub == 0, r, a.row_ptr[r + 1] - a.row_ptr[r], tot, o, q, nullptr,
-                                 a.partial + (static_cast<int64_t>(step_grid) + r) * a.kp);
+    finish_row<T, L, ZM, double>(a, sub == 0, r, a.row_ptr[r + 1] - a.row_ptr[r], tot, o, q, mom);
   }
-}
-
-// Block-level fixed-order reduction of the per-lane probe sums (LDS
-// s_mom[c][thread] for probe c of the thread's lane) into
-// partial[blockIdx.x][0..kp).
-template <typename T, int L>
-__device__ inline void block_partials(const StepArgs& a, const double (*s_mom)[kBlock]) {
-  constexpr int PPL = 16 / sizeof(T);
-  __syncthreads();
-  if (static_cast<int>(threadIdx.x) < a.kp) {
-    const int j = threadIdx.x, qq = j / PPL, cc = j % PPL;
-    double s = 0.0, comp = 0.0;
-    for (int t = qq; t < kBlock; t += L) neumaier(s, comp, s_mom[cc][t]);
-    a.partial[static_cast<int64_t>(blockIdx.x) * a.kp + j] = s + comp;
-  }
+  StepArgs b = a;
+  b.partial = a.partial + static_cast<int64_t>(step_grid) * a.kp;
+  block_partials<T, L>(b, s_mom);
 }
 
 template <typename T, int L, int U, int ZM>
@@ -487,9 +492,9 @@ __global__ __launch_bounds__(kBlock) void k_moment0(StepArgs a) {
     for (int c = 0; c < PPL; ++c) y[c] = static_cast<double>(z[c]);
     emit_moments<T, L>(a, own, o.node, y, z, q, mom);
   }
-  // no split rows at moment 0: clear their slots
+  // no split rows at moment 0: clear the finisher's slots
   double* sp = a.partial + static_cast<int64_t>(gridDim.x) * a.kp;
-  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < a.n_split * a.kp;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < int64_t(a.split_blocks) * a.kp;
        t += static_cast<int64_t>(gridDim.x) * kBlock)
     sp[t] = 0.0;
   block_partials<T, L>(a, s_mom);
@@ -724,8 +729,7 @@ nd_status launch_step_zm(const StepArgs& base, int grid, bool moment0, hipStream
     hipLaunchKernelGGL((k_cheb_step<T, L, 8, ZM>), dim3(grid), dim3(kBlock), 0, st, base);
     if (base.n_split > 0) {
       ND_LAUNCH_CHECK();
-      const int g2 = grid_for(base.n_split, kWavesPerBlock, grid);
-      hipLaunchKernelGGL((k_split_finish<T, L, ZM>), dim3(g2), dim3(kBlock), 0, st, base, grid);
+      hipLaunchKernelGGL((k_split_finish<T, L, ZM>), dim3(base.split_blocks), dim3(kBlock), 0, st, base, grid);
     }
   }
   ND_LAUNCH_CHECK();
@@ -790,7 +794,8 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     T* A = Z + static_cast<int64_t>(N) * kp;
     T* B = A + static_cast<int64_t>(N) * kp;
     const int grid = grid_for(sc->n_items > 0 ? sc->n_items : 1, kWavesPerBlock, step_grid<T>(L));
-    const int64_t slots = static_cast<int64_t>(grid) + sc->n_split;
+    const int split_blocks = sc->n_split > 0 ? grid_for(sc->n_split, kWavesPerBlock, grid) : 0;
+    const int64_t slots = static_cast<int64_t>(grid) + split_blocks;
     const int64_t per_step = slots * kp;
     int R = static_cast<int>((int64_t(64) << 20) / (per_step * 8));
     if (R < 1) R = 1;
@@ -841,6 +846,7 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     a.chunk_owner = sc->chunk_owner;
     a.chunk_nnz = sc->chunk_nnz;
     a.n_split = sc->n_split;
+    a.split_blocks = split_blocks;
     a.slot_nnz = sc->slot_nnz;
     a.zmode = zmode;
     a.seed = job.seed;

@@ -20,75 +20,127 @@ __device__ inline double jackson_g(int m, int M) {
   return (static_cast<double>(M - m + 1) * cos(a * m) + sin(a * m) * cos(a) / sin(a)) / static_cast<double>(M + 1);
 }
 
-// W[e][m] for the bin integral table (n_edges rows) followed by the density
-// table (n_points rows).
-__global__ __launch_bounds__(kBlock) void k_recon_table(int M, int kernel, int n_bins, double lo, double hi,
-                                                        int n_points, double* __restrict__ W) {
+// Column tiles of the product: kTC columns, kKC moments per LDS stage.
+constexpr int kTR = 64;  // rows per block
+constexpr int kTC = 64;  // columns per launch
+constexpr int kKC = 32;  // moments per stage
+
+// Table Wt[m][c] (m < Mp, c < cpad; zero beyond M and beyond the columns):
+// columns 0..n_edges-1 are the bin-edge integrals F, then n_points density
+// columns at the Chebyshev nodes.  Moment-major, so that a stage of kKC
+// moments of a column tile is one contiguous block.
+__global__ __launch_bounds__(kBlock) void k_recon_table(int M, int Mp, int kernel, int n_bins, double lo, double hi,
+                                                        int n_points, int cpad, double* __restrict__ Wt) {
   const int n_edges = n_bins > 0 ? n_bins + 1 : 0;
-  const int64_t total = static_cast<int64_t>(n_edges + n_points) * M;
+  const int64_t total = static_cast<int64_t>(Mp) * cpad;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; idx < total;
        idx += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const int r = static_cast<int>(idx / M), m = static_cast<int>(idx % M);
-    const double g = kernel ? jackson_g(m, M) : 1.0;
-    double w;
-    if (r < n_edges) {
-      double x = lo + (hi - lo) * static_cast<double>(r) / static_cast<double>(n_bins);
-      x = x < -1.0 ? -1.0 : (x > 1.0 ? 1.0 : x);
-      const double th = acos(x);
-      w = (m == 0) ? th : 2.0 * sin(static_cast<double>(m) * th) / static_cast<double>(m);
-    } else {
-      const int k = r - n_edges;
-      const double th = M_PI * (static_cast<double>(k) + 0.5) / static_cast<double>(n_points);
-      w = ((m == 0) ? 1.0 : 2.0 * cos(static_cast<double>(m) * th)) / (M_PI * sin(th));
+    const int m = static_cast<int>(idx / cpad), c = static_cast<int>(idx % cpad);
+    double w = 0.0;
+    if (m < M && c < n_edges + n_points) {
+      const double g = kernel ? jackson_g(m, M) : 1.0;
+      if (c < n_edges) {
+        double x = lo + (hi - lo) * static_cast<double>(c) / static_cast<double>(n_bins);
+        x = x < -1.0 ? -1.0 : (x > 1.0 ? 1.0 : x);
+        const double th = acos(x);
+        w = (m == 0) ? th : 2.0 * sin(static_cast<double>(m) * th) / static_cast<double>(m);
+      } else {
+        const int k = c - n_edges;
+        const double th = M_PI * (static_cast<double>(k) + 0.5) / static_cast<double>(n_points);
+        w = ((m == 0) ? 1.0 : 2.0 * cos(static_cast<double>(m) * th)) / (M_PI * sin(th));
+      }
+      w *= g;
     }
-    W[idx] = g * w;
+    Wt[idx] = w;
   }
 }
 
-// out[row][c] = sum_m mu[row][m] W[c][m] for c < ncols (fixed order in m).
-// A block handles kRows rows; their moment rows are staged in LDS.
-constexpr int kRows = 8;
-constexpr int kMaxStage = 1024;  // moments staged per pass
-
-__global__ __launch_bounds__(kBlock) void k_recon_apply(const double* __restrict__ mu, int64_t n_rows, int M,
-                                                        const double* __restrict__ W, int ncols,
-                                                        double* __restrict__ out, int ld_out,
-                                                        const double* __restrict__ corr) {
-  __shared__ double smu[kRows][kMaxStage];
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kRows;
-  const int work = kRows * ncols;
-  // each thread owns up to ceil(work / kBlock) (row, col) outputs
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int per = (work + kBlock - 1) / kBlock;  // <= 4 enforced by the host
-  for (int m0 = 0; m0 < M; m0 += kMaxStage) {
-    const int mm = M - m0 < kMaxStage ? M - m0 : kMaxStage;
+// out[row][c] = sum_m mu[row][m] Wt[m][c0 + c] - corr[c0 + c], c < ncols, for
+// one tile of kTC table columns: a block owns kTR rows, stages kKC moments of its rows and of
+// the column tile in LDS, and each thread accumulates a 4x4 register tile
+// (rows ty + 16 i, columns tx + 16 j) in a fixed order over m.
+// With `hist` set, the tile holds all n_bins + 1 edge columns and the block
+// writes the bin masses hist[row][b] = (F_b - F_{b+1}) / pi + spikes directly.
+__global__ __launch_bounds__(kBlock) void k_recon_gemm(const double* __restrict__ mu, int64_t n_rows, int M,
+                                                       const double* __restrict__ Wt, int cpad, int c0, int ncols,
+                                                       const double* __restrict__ corr, double* __restrict__ out,
+                                                       int ld_out, double* __restrict__ hist,
+                                                       const int32_t* __restrict__ sbin,
+                                                       const double* __restrict__ sw, int n_spikes) {
+  constexpr int kLdA = kKC + 1;
+  __shared__ double lds[kTR * (kTC + 1)];  // >= kTR * kLdA + kKC * kTC
+  static_assert(kTR * (kTC + 1) >= kTR * kLdA + kKC * kTC, "LDS tile too small");
+  double* sa = lds;                // [kTR][kLdA]
+  double* sb = lds + kTR * kLdA;   // [kKC][kTC]
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kTR;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int m0 = 0; m0 < M; m0 += kKC) {
+    const int mm = M - m0 < kKC ? M - m0 : kKC;
     __syncthreads();
-    for (int t = threadIdx.x; t < kRows * mm; t += kBlock) {
-      const int rr = t / mm, m = t % mm;
-      smu[rr][m] = (r0 + rr < n_rows) ? mu[(r0 + rr) * M + m0 + m] : 0.0;
+    for (int t = threadIdx.x; t < kTR * kKC; t += kBlock) {
+      const int r = t / kKC, k = t % kKC;
+      sa[r * kLdA + k] = (r0 + r < n_rows && k < mm) ? mu[(r0 + r) * M + m0 + k] : 0.0;
+    }
+    for (int t = threadIdx.x; t < kKC * kTC; t += kBlock) {
+      const int k = t / kTC, c = t % kTC;
+      sb[t] = Wt[static_cast<int64_t>(m0 + k) * cpad + c0 + c];
     }
     __syncthreads();
-    for (int u = 0; u < per; ++u) {
-      const int w = threadIdx.x + u * kBlock;
-      if (w >= work) break;
-      const int rr = w / ncols, c = w % ncols;
-      const double* wr = W + static_cast<int64_t>(c) * M + m0;
-      double s = acc[u];
-      for (int m = 0; m < mm; ++m) s = fma(smu[rr][m], wr[m], s);
-      acc[u] = s;
+#pragma unroll 8
+    for (int k = 0; k < kKC; ++k) {
+      double x[4], y[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = sa[(ty + 16 * i) * kLdA + k];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) y[j] = sb[k * kTC + tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(x[i], y[j], acc[i][j]);
     }
   }
-  for (int u = 0; u < per; ++u) {
-    const int w = threadIdx.x + u * kBlock;
-    if (w >= work) break;
-    const int rr = w / ncols, c = w % ncols;
-    if (r0 + rr < n_rows) out[(r0 + rr) * ld_out + c] = corr ? acc[u] - corr[c] : acc[u];
+  if (!hist) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = r0 + ty + 16 * i;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = tx + 16 * j;
+        if (r < n_rows && c < ncols) out[r * ld_out + c] = corr ? acc[i][j] - corr[c0 + c] : acc[i][j];
+      }
+    }
+    return;
+  }
+  // fused bins: F tile through LDS, then the differences of adjacent edges
+  constexpr int kLdF = kTC + 1;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = tx + 16 * j;
+      lds[(ty + 16 * i) * kLdF + c] = corr && c < ncols ? acc[i][j] - corr[c] : acc[i][j];
+    }
+  __syncthreads();
+  const int nb = ncols - 1;
+  for (int t = threadIdx.x; t < kTR * nb; t += kBlock) {
+    const int r = t / nb, b = t % nb;
+    if (r0 + r >= n_rows) break;
+    double h = (lds[r * kLdF + b] - lds[r * kLdF + b + 1]) / M_PI;
+    for (int s = 0; s < n_spikes; ++s)
+      if (sbin[s] == b) h += sw[s];
+    hist[(r0 + r) * nb + b] = h;
   }
 }
 
-// corr[c] = sum_s w_s sum_m T_m(lambda_s) W[c][m]: the part of column c that
+// corr[c] = sum_s w_s sum_m T_m(lambda_s) Wt[m][c]: the part of column c that
 // the point masses contribute when the moments include them.
-__global__ __launch_bounds__(kBlock) void k_spike_corr(const double* __restrict__ W, int ncols, int M,
+__global__ __launch_bounds__(kBlock) void k_spike_corr(const double* __restrict__ Wt, int cpad, int ncols, int M,
                                                        const double* __restrict__ lam, const double* __restrict__ w,
                                                        int n_spikes, double* __restrict__ corr) {
   for (int c = blockIdx.x * kBlock + threadIdx.x; c < ncols; c += gridDim.x * kBlock) {
@@ -97,7 +149,8 @@ __global__ __launch_bounds__(kBlock) void k_spike_corr(const double* __restrict_
       const double x = lam[s] < -1.0 ? -1.0 : (lam[s] > 1.0 ? 1.0 : lam[s]);
       const double th = acos(x);
       double t = 0.0;
-      for (int m = 0; m < M; ++m) t = fma(cos(static_cast<double>(m) * th), W[static_cast<int64_t>(c) * M + m], t);
+      for (int m = 0; m < M; ++m)
+        t = fma(cos(static_cast<double>(m) * th), Wt[static_cast<int64_t>(m) * cpad + c], t);
       acc += w[s] * t;
     }
     corr[c] = acc;
@@ -166,9 +219,13 @@ extern "C" nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_
     sbin.push_back(b);
     sw.push_back(spike_weight[s]);
   }
+  const int cpad = static_cast<int>(ceil_div(ncols, kTC)) * kTC;
+  const int Mp = static_cast<int>(ceil_div(n_moments, kKC)) * kKC;
+  // bins fused into the product when all edge columns fit one tile
+  const bool fused = nb > 0 && n_edges <= kTC;
   double *W = nullptr, *F = nullptr, *sw_d = nullptr, *corr = nullptr, *all_d = nullptr;
   int32_t* sb_d = nullptr;
-  nd_status s = dalloc_t(&W, static_cast<size_t>(ncols) * n_moments);
+  nd_status s = dalloc_t(&W, static_cast<size_t>(Mp) * cpad);
   if (s == ND_OK && spikes_in && n_spikes > 0) {
     s = dalloc_t(&corr, static_cast<size_t>(ncols));
     if (s == ND_OK) s = dalloc_t(&all_d, static_cast<size_t>(2 * n_spikes));
@@ -179,7 +236,7 @@ extern "C" nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_
       s = ND_EDEVICE;
     }
   }
-  if (s == ND_OK && nb) s = dalloc_t(&F, static_cast<size_t>(n_rows) * n_edges);
+  if (s == ND_OK && nb && !fused) s = dalloc_t(&F, static_cast<size_t>(n_rows) * n_edges);
   if (s == ND_OK && !sbin.empty()) s = dalloc_t(&sb_d, sbin.size());
   if (s == ND_OK && !sw.empty()) s = dalloc_t(&sw_d, sw.size());
   if (s == ND_OK && !sbin.empty()) {
@@ -190,38 +247,39 @@ extern "C" nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_
     }
   }
   if (s == ND_OK) {
-    hipLaunchKernelGGL(k_recon_table, dim3(grid_for(static_cast<int64_t>(ncols) * n_moments, kBlock)), dim3(kBlock),
-                       0, st, n_moments, static_cast<int>(kernel), nb, lo, hi, np, W);
+    hipLaunchKernelGGL(k_recon_table, dim3(grid_for(static_cast<int64_t>(Mp) * cpad, kBlock)), dim3(kBlock), 0, st,
+                       n_moments, Mp, static_cast<int>(kernel), nb, lo, hi, np, cpad, W);
     if (corr)
-      hipLaunchKernelGGL(k_spike_corr, dim3(grid_for(ncols, kBlock)), dim3(kBlock), 0, st, W, ncols, n_moments, all_d,
-                         all_d + n_spikes, n_spikes, corr);
-    // products: bins then points, each in column groups that fit a block
-    // products: bin-edge columns then point columns, in groups that fit a block
-    auto apply = [&](const double* Wc, const double* cc_corr, int cols, double* out) -> bool {
-      const int per_grp = (4 * kBlock) / kRows;
-      for (int c0 = 0; c0 < cols; c0 += per_grp) {
-        const int cc = cols - c0 < per_grp ? cols - c0 : per_grp;
-        hipLaunchKernelGGL(k_recon_apply, dim3(static_cast<unsigned>(ceil_div(n_rows, kRows))), dim3(kBlock), 0, st,
-                           mu, n_rows, n_moments, Wc + static_cast<int64_t>(c0) * n_moments, cc, out + c0, cols,
-                           cc_corr ? cc_corr + c0 : nullptr);
-        if (hipGetLastError() != hipSuccess) return false;
+      hipLaunchKernelGGL(k_spike_corr, dim3(grid_for(ncols, kBlock)), dim3(kBlock), 0, st, W, cpad, ncols, n_moments,
+                         all_d, all_d + n_spikes, n_spikes, corr);
+    const dim3 grid(static_cast<unsigned>(ceil_div(n_rows, kTR)));
+    bool ok = hipGetLastError() == hipSuccess;
+    // product over the table columns [c_begin, c_end), tile by tile, into o
+    // (row stride ld; its column 0 is table column c_begin)
+    auto apply = [&](int c_begin, int c_end, double* o, int ld) {
+      for (int c0 = c_begin; c0 < c_end && ok; c0 += kTC) {
+        const int cc = c_end - c0 < kTC ? c_end - c0 : kTC;
+        hipLaunchKernelGGL(k_recon_gemm, grid, dim3(kBlock), 0, st, mu, n_rows, n_moments, W, cpad, c0, cc, corr,
+                           o + (c0 - c_begin), ld, nullptr, nullptr, nullptr, 0);
+        ok = hipGetLastError() == hipSuccess;
       }
-      return true;
     };
-    bool ok = true;
-    if (nb) ok = apply(W, corr, n_edges, F);
-    if (ok && np) ok = apply(W + static_cast<int64_t>(n_edges) * n_moments, corr ? corr + n_edges : nullptr, np, rho);
+    if (fused) {
+      hipLaunchKernelGGL(k_recon_gemm, grid, dim3(kBlock), 0, st, mu, n_rows, n_moments, W, cpad, 0, n_edges, corr,
+                         nullptr, 0, hist, sb_d, sw_d, static_cast<int>(sbin.size()));
+      ok = ok && hipGetLastError() == hipSuccess;
+    } else if (nb) {
+      apply(0, n_edges, F, n_edges);
+      if (ok) {
+        hipLaunchKernelGGL(k_recon_bins, dim3(grid_for(n_rows * nb, kBlock)), dim3(kBlock), 0, st, F, n_rows, nb,
+                           sb_d, sw_d, static_cast<int>(sbin.size()), hist);
+        ok = hipGetLastError() == hipSuccess;
+      }
+    }
+    if (np) apply(n_edges, n_edges + np, rho, np);
     if (!ok) {
       set_error("nd_reconstruct: launch failed");
       s = ND_EDEVICE;
-    }
-    if (s == ND_OK && nb) {
-      hipLaunchKernelGGL(k_recon_bins, dim3(grid_for(n_rows * nb, kBlock)), dim3(kBlock), 0, st, F, n_rows, nb, sb_d,
-                         sw_d, static_cast<int>(sbin.size()), hist);
-      if (hipGetLastError() != hipSuccess) {
-        set_error("nd_reconstruct: launch failed");
-        s = ND_EDEVICE;
-      }
     }
   }
   // temporaries are released once the stream has consumed them

@@ -218,6 +218,39 @@ def test_reconstruct(nd):
             assert np.max(np.abs(rho.cpu().numpy().reshape(rows.shape[0], 64) - r_o)) < 1e-9
 
 
+@pytest.mark.parametrize("nb", [50, 63, 64])
+def test_reconstruct_tiles_and_spikes_in_moments(nd, nb):
+    """Several row tiles with a ragged last one, a moment count that is not a
+    multiple of the staging depth, bins fused into the product (nb + 1 <= 64
+    edge columns) or not, three density column tiles, and moments that carry
+    the point masses (ND_SPIKES_IN_MOMENTS): the result must equal the
+    histogram of the smooth moments plus the masses."""
+    import torch
+    n, s, d = sg.erdos_renyi(600, 0.01, seed=4)
+    g_or = og.build_csr(n, s, d)
+    M, K = 37, 130
+    mu, ldos = kpm.exact_moments_eig(og.normalized_adjacency(g_or), M)
+    smooth = np.vstack([mu[None, :], ldos[:149]])
+    spikes = [(0.0, 0.125), (-0.5, 0.0625), (1.0, 0.03125)]
+    m = np.arange(M)
+    full = smooth + sum(w * np.cos(m * np.arccos(lam)) for lam, w in spikes)[None, :]
+    rows = smooth.shape[0]
+    hist = _zeros(rows * nb, torch.float64)
+    rho = _zeros(rows * K, torch.float64)
+    nd.nd_reconstruct(_t(full), rows, M, nd.ND_KERNEL_JACKSON | nd.ND_SPIKES_IN_MOMENTS, spikes, nb, -1.0, 1.0,
+                      hist, K, rho)
+    h_o = rc.histogram(smooth, nb, -1.0, 1.0, kernel="jackson", spikes=spikes)
+    assert np.max(np.abs(hist.cpu().numpy().reshape(rows, nb) - h_o).sum(axis=1)) < 1e-10
+    # the density columns are the smooth part's series (point masses removed)
+    r_o = rc.density(smooth, rc.cheb_nodes(K), kernel="jackson")
+    assert np.max(np.abs(rho.cpu().numpy().reshape(rows, K) - r_o)) < 1e-9
+    # plain moments, no point masses: hist of the same rows
+    hist2 = _zeros(rows * nb, torch.float64)
+    nd.nd_reconstruct(_t(smooth), rows, M, nd.ND_KERNEL_NONE, (), nb, -1.0, 1.0, hist2)
+    h2 = rc.histogram(smooth, nb, -1.0, 1.0, kernel="none")
+    assert np.max(np.abs(hist2.cpu().numpy().reshape(rows, nb) - h2).sum(axis=1)) < 1e-10
+
+
 def test_errors(nd):
     import torch
     with pytest.raises(nd.NDError) as e:

@@ -101,7 +101,7 @@ def test_neighbor_sets_from_edges():
     nbs = og.neighbor_sets_from_edges(s, d, pick)
     for o in pick:
         i = int(np.searchsorted(g.old_id, o))
-        assert sorted(nbs[int(o)]) == sorted(g.old_id[g.neighbors(i)].tolist())
+        assert nbs[int(o)].tolist() == g.old_id[g.neighbors(i)].tolist()
 
 
 # ---------------------------------------------------------------- probes
@@ -135,3 +135,14 @@ def test_gaussian_stats():
         assert stats.kstest(Z[:, j], "norm").pvalue > 1e-4
     assert abs(Z.var() - 1.0) < 0.02
     assert np.array_equal(Z, Z.astype(np.float32).astype(np.float64))
+
+
+def test_rademacher_at_and_compact_ids():
+    Z = orng.rademacher(300, 5, seed=9)
+    pick = np.array([0, 17, 299, 5])
+    assert np.array_equal(orng.rademacher_at(pick, 5, 9), Z[pick])
+    n, s, d = sg.rmat(11, 4, seed=2)
+    g = og.build_csr(n, s, d)
+    cid = og.compact_ids_from_edges(n, s, d)
+    assert np.array_equal(cid[g.old_id], np.arange(g.n))
+    assert np.sum(cid >= 0) == g.n
