@@ -80,6 +80,26 @@ def profiled_traffic(workload: str):
     return None
 
 
+def copy_bandwidth_gbs(reps: int = 5) -> float:
+    """Achievable HBM bandwidth of a plain 1 GiB device-to-device copy (read +
+    write bytes over time, HIP events), the practical ceiling beside the
+    datasheet peak."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -304,6 +324,7 @@ def main():
     b_launch = algorithmic_bytes(n, nnz, k, W.ldos)
     achieved = b_launch / (avg_launch_ms * 1e-3) / 1e9
     traffic = profiled_traffic(args.workload)
+    copy_gbs = copy_bandwidth_gbs()
     mu = out["mu"].cpu().numpy()
     line = {
         "metric": METRIC,
@@ -323,8 +344,10 @@ def main():
                    "ldos": W.ldos, "state": "fp32 recurrence, fp64 compensated moment sums"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_GBs": round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1) if traffic else None,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
                      "kernel": "k_cheb_step", "avg_launch_ms": round(avg_launch_ms, 5),
+                     "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                      "algorithmic_bytes_per_launch": b_launch},
         "spmm_only_G_per_s": round(work / (kern_ms * 1e-3 / args.steps) / 1e9, 3) if kern_ms else None,
         "mu_head": [round(float(x), 6) for x in mu[:4]],
