@@ -136,6 +136,65 @@ def cpu_baseline(workload: str, k: int, ldos: bool, seed: int):
             "sample": sample + "; fp64 numpy/scipy single thread, %.2f s, host CPU: %s" % (dt, cpu_model())}
 
 
+def precision_study(args) -> dict:
+    """fp32 against fp64 recurrence state at the precision-study workload
+    (R-MAT scale 22 ef 16, 32 probes, 1000 moments): the drift of the global
+    moments, the per-node moments and the 200-bin global density with the
+    moment index, and the step time of both states.  The fp64-state path is
+    the reference here; the parity tests pin it to the oracle at M = 1000."""
+    import torch
+    import paper_1905_09758_amd as nd
+    from synthgraph.workloads import WORKLOADS
+    W = WORKLOADS["rmat22"]
+    k, M, bins = W.probes, W.moments, W.bins
+    n_nodes, src, dst = W.graph(args.seed)
+    g = nd.nd_build_csr(n_nodes, torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda())
+    del src, dst
+    f64 = torch.float64
+    out = {"workload": "rmat22", "graph": W.describe, "n": g.n, "nnz": g.nnz, "probes": k, "moments": M}
+    res = {}
+    for name, flag in (("fp32", 0), ("fp64", nd.ND_STATE_FP64)):
+        mu = torch.empty(M, dtype=f64, device="cuda")
+        pp = torch.empty(k * M, dtype=f64, device="cuda")
+        nd.nd_cheb_moments(g, None, k, M, args.seed, flag | nd.ND_TIME_STEPS, mu, pp)
+        ms, nl = nd.nd_graph_step_timing(g)
+        hist = torch.empty(bins, dtype=f64, device="cuda")
+        nd.nd_reconstruct(mu, 1, M, nd.ND_KERNEL_JACKSON, (), bins, -1.0, 1.0, hist)
+        res[name] = (mu, pp.view(k, M), hist)
+        sb = 8 if flag else 4
+        avg = ms / max(nl, 1)
+        out["step_ms_" + name] = round(avg, 4)
+        out["algorithmic_GBs_" + name] = round(algorithmic_bytes(g.n, g.nnz, k, False, sb) / (avg * 1e-3) / 1e9, 1)
+    torch.cuda.synchronize()
+    eps = 2.0 ** -24
+    m = np.arange(M, dtype=np.float64)
+    d_mu = (res["fp32"][0] - res["fp64"][0]).abs().cpu().numpy()
+    d_pp = (res["fp32"][1] - res["fp64"][1]).abs().amax(dim=0).cpu().numpy()
+    out["global_max_abs_err_m<=200"] = float(d_mu[:201].max())
+    out["global_max_abs_err"] = float(d_mu.max())
+    out["per_probe_max_abs_err"] = float(d_pp.max())
+    out["density_L1_200bins"] = float((res["fp32"][2] - res["fp64"][2]).abs().sum().item())
+    del res
+    # per-node moments: both states, compared on the device
+    ld = {}
+    for name, flag in (("fp32", 0), ("fp64", nd.ND_STATE_FP64)):
+        ld[name] = torch.empty(g.n * M, dtype=f64, device="cuda")
+        nd.nd_ldos_moments(g, None, k, M, args.seed, flag, ld[name])
+    d_ld = (ld["fp32"].view(g.n, M) - ld["fp64"].view(g.n, M)).abs_().amax(dim=0).cpu().numpy()
+    del ld
+    torch.cuda.empty_cache()
+    out["ldos_max_abs_err_m<=200"] = float(d_ld[:201].max())
+    out["ldos_max_abs_err"] = float(d_ld.max())
+    mm = np.maximum(m[1:], 1.0)
+    out["envelope_c_linear"] = {"global": float((d_mu[1:] / (mm * eps)).max()),
+                                "ldos": float((d_ld[1:] / (mm * eps)).max())}
+    out["envelope_c_quadratic"] = {"global": float((d_mu[1:] / (mm * mm * eps)).max()),
+                                   "ldos": float((d_ld[1:] / (mm * mm * eps)).max())}
+    out["ldos_err_at"] = {str(i): float(d_ld[i]) for i in (1, 10, 50, 100, 200, 400, 600, 800, 999) if i < M}
+    out["global_err_at"] = {str(i): float(d_mu[i]) for i in (1, 10, 50, 100, 200, 400, 600, 800, 999) if i < M}
+    return out
+
+
 def cv_study(args) -> dict:
     """Learned control variate (config 5): train on synthetic graphs of four
     families with LDOS targets from the method itself, then compare the
@@ -238,6 +297,8 @@ def main():
     ap.add_argument("--cv-target-probes", type=int, default=1024)
     ap.add_argument("--cv-steps", type=int, default=3000)
     ap.add_argument("--no-filter", action="store_true", help="skip twin filtering (ba1m_twins)")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="fp32 vs fp64 recurrence state on R-MAT scale 22 (32 probes, 1000 moments)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -262,6 +323,9 @@ def main():
     nd.require_gpu()
     if args.workload == "cv5":
         print(json.dumps(cv_study(args)), flush=True)
+        return
+    if args.precision_study:
+        print(json.dumps(precision_study(args)), flush=True)
         return
     W = WORKLOADS[args.workload]
     k, M = W.probes, W.moments

@@ -128,6 +128,37 @@ def test_global_moments_fp64_state(case, nd):
     assert np.max(np.abs(mu.cpu().numpy() - mu_o)) < TOL_FP64
 
 
+def test_moments_m1000(nd):
+    """The precision-study moment count (M = 1000) on a small R-MAT graph.
+    fp64 state: within 1e-9 of the oracle (fp64 rounding, amplified like the
+    fp32 case, stays ~m^2 2^-53).  fp32 state: global moments within 1e-5 up to
+    m = 200 as everywhere; beyond, global and per-node moments within the
+    worst-case envelope m^2 2^-24 (rounding errors reach moment m through
+    U_{m-k}(H), as large as m-k+1 at the eigenvalues +-1; on this small graph
+    the hubs carry a large share of the Perron vector, so the per-node error
+    does grow faster than linearly: about 1% of m^2 2^-24 at m = 999)."""
+    import torch
+    n, s, d = sg.rmat(12, 8, seed=3)
+    g_or = og.build_csr(n, s, d)
+    g = nd.nd_build_csr(n, s, d)
+    k, M = 32, 1000
+    H = og.normalized_adjacency(g_or)
+    Z = orng.rademacher(g_or.n, k, 4)
+    mu_o, _, C_o = kpm.stochastic_moments(H, Z, M)
+    mu = _zeros(M, torch.float64)
+    nd.nd_cheb_moments(g, None, k, M, 4, nd.ND_STATE_FP64, mu)
+    assert np.max(np.abs(mu.cpu().numpy() - mu_o)) < 1e-9
+    ld = _zeros(g.n * M, torch.float64)
+    mu32 = _zeros(M, torch.float64)
+    nd.nd_ldos_moments(g, None, k, M, 4, 0, ld, mu=mu32)
+    err_mu = np.abs(mu32.cpu().numpy() - mu_o)
+    assert err_mu[:201].max() < TOL_MU
+    err = np.abs(ld.cpu().numpy().reshape(g.n, M) - C_o).max(axis=0)
+    env = np.maximum(1e-5, np.arange(M, dtype=np.float64) ** 2 * EPS32)
+    assert np.all(err <= env), (int(np.argmax(err / env)), float(np.max(err / env)))
+    assert np.all(err_mu <= env)
+
+
 @pytest.mark.parametrize("k,M", [(20, 50), (70, 12)])
 def test_ldos(case, nd, k, M):
     import torch
