@@ -1,10 +1,21 @@
-"""Twin motifs and probe projection (Sec. 3.4, motif filtering).
+"""Twin motifs and probe projection (Sec. 3.4, motif filtering; Sec. 3.3
+for the spectral signature of the motifs).
+
+Oracle: test infrastructure only (tests, the smoke check and the CPU baseline
+of the benchmark use it; the GPU library never does).
 
 Two nodes with identical open neighbourhoods ("node copies", e.g. two dangling
 nodes on the same neighbour) carry a localized eigenvector e_i - e_j with
 eigenvalue 0 of the normalized adjacency: the columns i and j of H are equal
 up to the scale 1/sqrt(d_i) = 1/sqrt(d_j), so H(e_i - e_j) = 0.  A class C of
 |C| mutual twins contributes |C| - 1 such eigenvalues.
+
+Two adjacent nodes with identical closed neighbourhoods N[i] = N(i) + {i}
+(e.g. the two blade nodes of a triangle hanging off a hub) have equal degree
+d and A(e_i - e_j) = e_j - e_i, so H(e_i - e_j) = -(1/d)(e_i - e_j): a class
+C of such nodes contributes |C| - 1 eigenvalues at -1/d (the spikes at -1/2,
+-1/3, ... of the paper's spectra).  A node cannot have twins of both kinds
+(an open twin j and a closed twin k would force k ~ j, hence j in N[i]).
 
 The paper detects them with a random hash w = Hz (equal w_i = w_j with high
 probability means equal neighbourhoods); here the oracle groups nodes by the
@@ -28,16 +39,45 @@ from __future__ import annotations
 import numpy as np
 
 
-def twin_classes(g) -> list:
-    """Classes of >= 2 nodes with identical open neighbourhoods, in canonical
-    order: classes by smallest member, members ascending."""
+def twin_classes(g, kind: str = "open") -> list:
+    """Classes of >= 2 nodes with identical open neighbourhoods (kind
+    "open"), identical closed neighbourhoods ("closed"), or both kinds
+    ("both"; the two never share a node), in canonical order: classes by
+    smallest member, members ascending."""
+    if kind == "both":
+        classes = twin_classes(g, "open") + twin_classes(g, "closed")
+        classes.sort(key=lambda c: c[0])
+        return classes
+    if kind not in ("open", "closed"):
+        raise ValueError(kind)
     groups = {}
     for i in range(g.n):
-        key = g.col[g.row_ptr[i]:g.row_ptr[i + 1]].tobytes()
+        nb = g.col[g.row_ptr[i]:g.row_ptr[i + 1]]
+        key = tuple(sorted(nb.tolist() + [i])) if kind == "closed" else nb.tobytes()
         groups.setdefault(key, []).append(i)
     classes = [sorted(v) for v in groups.values() if len(v) >= 2]
     classes.sort(key=lambda c: c[0])
     return classes
+
+
+def class_eigenvalue(g, cls) -> float:
+    """The eigenvalue of H on the differences inside a class: 0 for open
+    twins (members not adjacent), -1/d for closed twins (members adjacent,
+    common degree d)."""
+    a, b = cls[0], cls[1]
+    nb = g.col[g.row_ptr[a]:g.row_ptr[a + 1]]
+    if b in set(nb.tolist()):
+        return -1.0 / float(nb.size)
+    return 0.0
+
+
+def spikes(classes, lambdas, n: int) -> list:
+    """Point masses removed from the DOS: [(lambda, sum over classes with that
+    eigenvalue of (|C| - 1) / N)], ascending in lambda."""
+    acc = {}
+    for c, lam in zip(classes, lambdas):
+        acc[lam] = acc.get(lam, 0) + len(c) - 1
+    return [(lam, acc[lam] / float(n)) for lam in sorted(acc)]
 
 
 def classes_to_arrays(classes):
@@ -88,16 +128,35 @@ def basis_dense(classes, n: int) -> np.ndarray:
     return np.stack(cols, axis=1) if cols else np.zeros((n, 0))
 
 
-def filtered_moments(H, Z: np.ndarray, M: int, classes, ldos: bool = True):
-    """Filtered estimates as in the module docstring.
+def cheb_at(lam: float, M: int) -> np.ndarray:
+    """T_m(lambda), m = 0..M-1, by the three-term recurrence (exact
+    {1, 0, -1, 0, ...} at lambda = 0)."""
+    t = np.zeros(M)
+    if M > 0:
+        t[0] = 1.0
+    if M > 1:
+        t[1] = lam
+    for m in range(1, M - 1):
+        t[m + 1] = 2.0 * lam * t[m] - t[m - 1]
+    return t
+
+
+def filtered_moments(H, Z: np.ndarray, M: int, classes, ldos: bool = True, lambdas=None):
+    """Filtered estimates as in the module docstring, for classes whose
+    removed eigenvalues are `lambdas` (all 0, open twins, when omitted):
+        mu_m = smooth part + sum_C (|C|-1)/N T_m(lambda_C)
+        C_im = smooth part + [i in C] (1 - 1/|C|) T_m(lambda_C).
     Returns (mu_full [M], mu_smooth [M], mu_pp_smooth [k][M], C [N][M] or None)."""
-    from .kpm import stochastic_moments, cheb_at_zero
+    from .kpm import stochastic_moments
     n = Z.shape[0]
+    if lambdas is None:
+        lambdas = [0.0] * len(classes)
     Zr = project(Z, classes)
     mu_s, mu_pp, C = stochastic_moments(H, Zr, M, ldos=ldos)
-    t0 = cheb_at_zero(M)
-    mu_full = mu_s + spike_weight(classes, n) * t0
+    mu_full = np.array(mu_s, copy=True)
+    for lam, w in spikes(classes, lambdas, n):
+        mu_full += w * cheb_at(lam, M)
     if ldos:
-        for c in classes:
-            C[np.asarray(c), :] += (1.0 - 1.0 / len(c)) * t0[None, :]
+        for c, lam in zip(classes, lambdas):
+            C[np.asarray(c), :] += (1.0 - 1.0 / len(c)) * cheb_at(lam, M)[None, :]
     return mu_full, mu_s, mu_pp, C

@@ -159,3 +159,29 @@ def star(s: int):
 def complete_bipartite(a: int, b: int):
     u, v = np.meshgrid(np.arange(a), np.arange(a, a + b), indexing="ij")
     return a + b, u.ravel().astype(np.int32), v.ravel().astype(np.int32)
+
+
+def friendship(k: int):
+    """Windmill of k triangles on hub 0: blade q is the adjacent pair
+    (2q+1, 2q+2), both joined to the hub."""
+    q = np.arange(k, dtype=np.int32)
+    a, b = 2 * q + 1, 2 * q + 2
+    hub = np.zeros(k, np.int32)
+    return 2 * k + 1, np.concatenate([a, a, b]), np.concatenate([b, hub, hub])
+
+
+def plant_adjacent_pairs(n: int, src, dst, pairs: int, seed: int, hubs=(1, 2, 3)):
+    """Append `pairs` new adjacent node pairs (ids n + 2q, n + 2q + 1); pair q
+    is joined, both nodes, to h distinct nodes drawn uniformly from [0, n),
+    h cycling through `hubs`.  Returns (n + 2 * pairs, src, dst)."""
+    rng = np.random.default_rng(seed)
+    s_add, d_add = [], []
+    for q in range(pairs):
+        u, v = n + 2 * q, n + 2 * q + 1
+        h = hubs[q % len(hubs)]
+        targets = rng.choice(n, size=h, replace=False)
+        s_add += [u] + [u] * h + [v] * h
+        d_add += [v] + list(targets) + list(targets)
+    src = np.concatenate([np.asarray(src, np.int32), np.asarray(s_add, np.int32)])
+    dst = np.concatenate([np.asarray(dst, np.int32), np.asarray(d_add, np.int32)])
+    return n + 2 * pairs, src, dst

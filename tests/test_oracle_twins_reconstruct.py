@@ -165,3 +165,164 @@ def test_exact_moment_histogram_nonnegative_and_spikes():
 def test_exact_histogram_snaps_edges():
     e = rc.exact_histogram(np.array([0.0, 1e-12, -1e-12, 0.5, 1.0]), 4)
     assert np.allclose(e, [0.0, 0.0, 0.6, 0.4], atol=1e-15)
+
+
+# ------------------------------------------------------------ closed (true) twins
+def brute_closed_twins(g):
+    nb = [frozenset(g.neighbors(i).tolist()) | {i} for i in range(g.n)]
+    seen, classes = set(), []
+    for i in range(g.n):
+        if i in seen:
+            continue
+        c = [j for j in range(i, g.n) if nb[j] == nb[i]]
+        if len(c) >= 2:
+            classes.append(c)
+            seen.update(c)
+    return classes
+
+
+def _mixed_graph(seed, n=120, p=0.03, open_pairs=6, closed_pairs=9):
+    n0, s, d = sg.erdos_renyi(n, p, seed=seed)
+    # dangling pairs (open twins) on random hubs, then adjacent pairs (closed twins)
+    rng = np.random.default_rng(seed + 1)
+    hubs = rng.choice(n0, open_pairs, replace=False)
+    extra_s = np.concatenate([np.arange(n0, n0 + 2 * open_pairs)]).astype(np.int32)
+    extra_d = np.repeat(hubs, 2).astype(np.int32)
+    s, d = np.concatenate([s, extra_s]), np.concatenate([d, extra_d])
+    return sg.plant_adjacent_pairs(n0 + 2 * open_pairs, s, d, closed_pairs, seed + 2)
+
+
+@pytest.mark.parametrize("gen", [_mixed_graph(1), _mixed_graph(2), sg.friendship(7), sg.complete(6),
+                                 sg.rmat(9, 4, seed=4)])
+def test_closed_twins_match_bruteforce(gen):
+    g, _ = graph_of(gen)
+    assert twins.twin_classes(g, "closed") == brute_closed_twins(g)
+    # the two kinds never share a node, and "both" is their canonical union
+    o, c = twins.twin_classes(g, "open"), twins.twin_classes(g, "closed")
+    assert not (set(x for k in o for x in k) & set(x for k in c for x in k))
+    assert twins.twin_classes(g, "both") == sorted(o + c, key=lambda k: k[0])
+
+
+def test_closed_twins_textbook():
+    # K_n: every node is a closed twin of every other; H has eigenvalues 1 and
+    # -1/(n-1) with multiplicity n-1
+    for n in (2, 3, 6):
+        g, H = graph_of(sg.complete(n))
+        cls = twins.twin_classes(g, "closed")
+        assert cls == [list(range(n))]
+        assert twins.class_eigenvalue(g, cls[0]) == -1.0 / (n - 1)
+        lam = np.sort(np.linalg.eigvalsh(H.toarray()))
+        assert np.allclose(lam, [-1.0 / (n - 1)] * (n - 1) + [1.0], atol=1e-13)
+    # friendship graph: k blades, each a class of 2 at -1/2
+    g, _ = graph_of(sg.friendship(5))
+    cls = twins.twin_classes(g, "closed")
+    assert cls == [[2 * q + 1, 2 * q + 2] for q in range(5)]
+    assert all(twins.class_eigenvalue(g, c) == -0.5 for c in cls)
+    assert twins.spikes(cls, [-0.5] * 5, g.n) == [(-0.5, 5 / 11)]
+    # open twins have eigenvalue 0; C_4 has only open twins
+    g, _ = graph_of(sg.cycle(4))
+    assert twins.twin_classes(g, "closed") == []
+    assert [twins.class_eigenvalue(g, c) for c in twins.twin_classes(g)] == [0.0, 0.0]
+
+
+def test_mixed_twins_eigenvectors_and_projection_spectrum():
+    g, H = graph_of(_mixed_graph(3))
+    cls = twins.twin_classes(g, "both")
+    lams = [twins.class_eigenvalue(g, c) for c in cls]
+    assert any(l < 0 for l in lams) and any(l == 0 for l in lams)
+    Hd = H.toarray()
+    for c, lam in zip(cls, lams):
+        for j in c[1:]:
+            v = np.zeros(g.n)
+            v[c[0]], v[j] = 1.0, -1.0
+            assert np.allclose(Hd @ v, lam * v, atol=1e-14)
+    P = twins.basis_dense(cls, g.n)
+    lam_h = list(np.sort(np.linalg.eigvalsh(Hd)))
+    lam_r = np.sort(np.linalg.eigvalsh(P.T @ Hd @ P))
+    for lam, w in twins.spikes(cls, lams, g.n):
+        for _ in range(int(round(w * g.n))):
+            k = int(np.argmin(np.abs(np.array(lam_h) - lam)))
+            assert abs(lam_h[k] - lam) < 1e-10
+            lam_h.pop(k)
+    assert np.allclose(np.sort(lam_h), lam_r, atol=1e-10)
+
+
+def test_filtered_estimates_with_closed_twins_unbiased_by_enumeration():
+    # friendship(2) + a dangling pair on the hub + an extra path: open and
+    # closed classes; all 2^n sign vectors
+    n, s, d = sg.friendship(2)
+    s = np.concatenate([s, np.array([0, 0, 1], np.int32)])
+    d = np.concatenate([d, np.array([5, 6, 7], np.int32)])
+    g, H = graph_of((8, s, d))
+    cls = twins.twin_classes(g, "both")
+    lams = [twins.class_eigenvalue(g, c) for c in cls]
+    assert sorted(lams) == [-0.5, 0.0]
+    Z = np.array(list(itertools.product([-1.0, 1.0], repeat=g.n))).T
+    M = 9
+    mu_full, _, _, C = twins.filtered_moments(H, Z, M, cls, lambdas=lams)
+    mu_x, l_x = kpm.exact_moments_eig(H, M)
+    assert np.allclose(mu_full, mu_x, atol=1e-12)
+    assert np.allclose(C, l_x, atol=1e-12)
+
+
+def test_cheb_at_matches_cosine():
+    for lam in (0.0, -0.5, -1.0 / 3.0, 0.9, -1.0, 1.0):
+        t = twins.cheb_at(lam, 40)
+        assert np.allclose(t, np.cos(np.arange(40) * np.arccos(lam)), atol=1e-12)
+    assert twins.cheb_at(0.0, 8).tolist() == [1.0, 0.0, -1.0, 0.0, 1.0, 0.0, -1.0, 0.0]
+
+
+# ------------------------------------------------------------ the paper's motif figure
+def _read_motifs(path):
+    blocks, cur = [], None
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        key, *rest = line.split()
+        if key == "motif":
+            cur = {"name": rest[0], "vector": None, "vector_rw": None}
+            blocks.append(cur)
+        elif key == "lambda":
+            cur["lambda"] = [float(x) for x in rest]
+        elif key == "edges":
+            cur["edges"] = [tuple(int(v) for v in e.split("-")) for e in rest]
+        elif key in ("vector", "vector_rw"):
+            cur[key] = {int(a): float(b) for a, b in (x.split(":") for x in rest)}
+    return blocks
+
+
+def test_paper_motif_figure_spikes():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "motif_spikes.txt")
+    motifs = _read_motifs(path)
+    assert len(motifs) == 6
+    for mo in motifs:
+        _, hs, hd = sg.complete(5)
+        n = 1 + max(max(e) for e in mo["edges"])
+        s = np.concatenate([hs, np.array([e[0] for e in mo["edges"]], np.int32)])
+        d = np.concatenate([hd, np.array([e[1] for e in mo["edges"]], np.int32)])
+        g, H = graph_of((n, s, d))
+        Hd = H.toarray()
+        lam_all = np.linalg.eigvalsh(Hd)
+        for lam in mo["lambda"]:
+            assert np.min(np.abs(lam_all - lam)) < 1e-12, (mo["name"], lam)
+        v = np.zeros(g.n)
+        if mo["vector"]:
+            for i, x in mo["vector"].items():
+                v[i] = x
+        elif mo["vector_rw"]:
+            for i, x in mo["vector_rw"].items():
+                v[i] = x * np.sqrt(g.deg[i])
+        if v.any():
+            assert np.allclose(Hd @ v, mo["lambda"][0] * v, atol=1e-13), mo["name"]
+    # the two panels that are twin motifs: classes and eigenvalues
+    by = {mo["name"]: mo for mo in motifs}
+    for name, kind, lam in (("dangling_pair", "open", 0.0), ("triangle_blade", "closed", -0.5)):
+        mo = by[name]
+        _, hs, hd = sg.complete(5)
+        s = np.concatenate([hs, np.array([e[0] for e in mo["edges"]], np.int32)])
+        d = np.concatenate([hd, np.array([e[1] for e in mo["edges"]], np.int32)])
+        g, _ = graph_of((7, s, d))
+        cls = twins.twin_classes(g, kind)
+        assert [5, 6] in cls and twins.class_eigenvalue(g, [5, 6]) == lam
