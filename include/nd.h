@@ -69,6 +69,8 @@ typedef struct nd_motifs nd_motifs; /* twin classes found in a graph */
                                      host synchronisation at the end of the call) */
 
 #define ND_TWINS_OPEN 0x1u        /* nd_motif_filter: nodes with equal open neighbourhoods */
+#define ND_TWINS_CLOSED 0x2u      /* nd_motif_filter: adjacent nodes with equal closed
+                                     neighbourhoods N(i) + {i} */
 
 #define ND_KERNEL_NONE 0u         /* nd_reconstruct: plain truncated series */
 #define ND_KERNEL_JACKSON 1u      /* nd_reconstruct: Jackson damping factors */
@@ -115,13 +117,19 @@ void nd_graph_free(nd_graph* g);
 
 /* --------------------------------------------------------------- motifs */
 
-/* Twin detection (Sec. 3.4): nodes whose open neighbourhoods are equal share
- * the localized eigenvectors e_i - e_j with eigenvalue 0.  Candidates come
- * from a random hash of each neighbourhood, h_i = sum_{j in N(i)} r_j over
- * Z/2^64 with seeded random r (the paper hashes with w = Hz); every candidate
- * class is then confirmed by exact comparison of sorted neighbour lists, so
- * the partition does not depend on the seed.
- *   kinds  ND_TWINS_OPEN (the only kind implemented).
+/* Twin detection (Sec. 3.4 and its motif figure).  Nodes whose open
+ * neighbourhoods are equal share the localized eigenvectors e_i - e_j with
+ * eigenvalue 0 (the paper's node copies).  Adjacent nodes whose closed
+ * neighbourhoods N(i) + {i} are equal have a common degree d and share
+ * eigenvectors e_i - e_j with eigenvalue -1/d (the blade motif at -1/2 and
+ * the -1/m family: an edge attached through the same m-1 nodes).  A node
+ * cannot have twins of both kinds, so the classes never overlap.
+ * Candidates come from a random hash of each neighbourhood,
+ * h_i = sum_{j in N(i)} r_j (+ r_i for closed neighbourhoods) over Z/2^64 with
+ * seeded random r (the paper hashes with w = Hz); every candidate class is
+ * then confirmed by exact comparison of sorted neighbour lists, so the
+ * partition does not depend on the seed.
+ *   kinds  ND_TWINS_OPEN, ND_TWINS_CLOSED or both.
  * Output classes (size >= 2) are in canonical order: by smallest member,
  * members ascending.  Synchronises `stream`.
  * Errors: ND_EINVAL, ND_EUNSUPPORTED (other kinds), ND_ENOMEM, ND_EDEVICE. */
@@ -129,14 +137,19 @@ nd_status nd_motif_filter(const nd_graph* g, uint64_t seed, uint32_t kinds, void
                           nd_motifs** out);
 
 /* Counts and spikes (host outputs; any may be NULL).  A twin class C removes
- * |C|-1 eigenvalues at 0; the single spike reported is lambda = 0 with weight
- * sum_C (|C|-1) / N (a fraction of the DOS mass).  spike_lambda/spike_weight
- * need room for 1 entry. */
+ * |C|-1 eigenvalues at lambda_C (0 or -1/d); the spikes are the distinct
+ * lambda_C in ascending order, each with weight sum (|C|-1) / N over its
+ * classes (a fraction of the DOS mass).  spike_lambda/spike_weight need room
+ * for *n_spikes entries: call once with them NULL to learn the count. */
 nd_status nd_motif_info(const nd_motifs* m, int64_t* n_classes, int64_t* n_motif_nodes,
                         int32_t* n_spikes, double* spike_lambda, double* spike_weight);
 
 /* Host copies: class_ptr int64 [n_classes+1], members int32 [n_motif_nodes]. */
 nd_status nd_motif_export(const nd_motifs* m, int64_t* class_ptr, int32_t* members);
+
+/* Host copy of each class's removed eigenvalue, double [n_classes]: 0 for
+ * open twins, -1/d for closed twins of degree d. */
+nd_status nd_motif_export_lambda(const nd_motifs* m, double* class_lambda);
 
 void nd_motifs_free(nd_motifs* m);
 
@@ -165,8 +178,8 @@ nd_status nd_make_probes(const nd_graph* g, const nd_motifs* motifs, int32_t n_p
  *   flags    ND_PROBE_RADEMACHER | ND_PROBE_GAUSSIAN, optionally ND_STATE_FP64
  *   motifs   NULL, or twin classes to filter: the probes are projected and
  *            mu/mu_pp hold the moments of the remaining (smooth) spectrum;
- *            the full-DOS moments are mu[m] + w T_m(0) with the spike weight
- *            w of nd_motif_info (T_m(0) = 1, 0, -1, 0, ...).
+ *            the full-DOS moments are mu[m] + sum_s w_s T_m(lambda_s) over
+ *            the spikes (lambda_s, w_s) of nd_motif_info.
  *   mu       device double [n_moments]
  *   mu_pp    device double [n_probes][n_moments], or NULL
  * The recurrence state is fp32 (fp64 with ND_STATE_FP64); every moment is
@@ -184,7 +197,8 @@ nd_status nd_cheb_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
  *            estimate exactly).
  *   motifs   NULL, or twin classes: probes projected as in nd_cheb_moments,
  *            and each class member i gets the removed part back exactly,
- *            ldos[i][m] += (1 - 1/|C|) T_m(0), so rows stay unbiased.
+ *            ldos[i][m] += (1 - 1/|C|) T_m(lambda_C), so rows stay unbiased
+ *            (mu then includes sum_s w_s T_m(lambda_s) over the spikes).
  *   ldos     device double [N][n_moments]
  *   ldos_sq  NULL, or device double [N][n_moments]: (1/k) sum_j v_ijm^2,
  *            for the per-probe variance ldos_sq - ldos^2.
@@ -213,7 +227,7 @@ nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
  * before the series, so hist is the smooth part's plus the exact masses and
  * rho is the smooth part's density.
  * Errors: ND_EINVAL for null pointers or sizes outside the ranges above
- * (n_bins, n_points in 1..4096, n_spikes in 0..64); ND_ENOMEM / ND_EDEVICE
+ * (n_bins, n_points in 1..4096, n_spikes in 0..1024); ND_ENOMEM / ND_EDEVICE
  * from the device.  The call synchronises the stream before it returns
  * (it releases its temporary tables). */
 nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_moments, uint32_t kernel,

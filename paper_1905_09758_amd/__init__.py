@@ -24,6 +24,7 @@ ND_OK, ND_EINVAL, ND_ENOMEM, ND_EDEVICE, ND_EOVERFLOW, ND_EUNSUPPORTED = 0, -1, 
 ND_INPUT_DEVICE = 0x1
 ND_PROBE_RADEMACHER, ND_PROBE_GAUSSIAN, ND_STATE_FP64, ND_TIME_STEPS = 0x0, 0x1, 0x2, 0x4
 ND_TWINS_OPEN = 0x1
+ND_TWINS_CLOSED = 0x2
 ND_KERNEL_NONE, ND_KERNEL_JACKSON, ND_SPIKES_IN_MOMENTS = 0, 1, 0x10
 
 _STATUS = {ND_EINVAL: "ND_EINVAL", ND_ENOMEM: "ND_ENOMEM", ND_EDEVICE: "ND_EDEVICE",
@@ -33,7 +34,8 @@ _STATUS = {ND_EINVAL: "ND_EINVAL", ND_ENOMEM: "ND_ENOMEM", ND_EDEVICE: "ND_EDEVI
 EXPORTS = (
     "nd_build_csr", "nd_graph_info", "nd_graph_export", "nd_graph_device_arrays", "nd_graph_step_timing",
     "nd_graph_free",
-    "nd_motif_filter", "nd_motif_info", "nd_motif_export", "nd_motifs_free", "nd_make_probes",
+    "nd_motif_filter", "nd_motif_info", "nd_motif_export", "nd_motif_export_lambda", "nd_motifs_free",
+    "nd_make_probes",
     "nd_cheb_moments", "nd_ldos_moments", "nd_reconstruct", "nd_node_features", "nd_column_stats",
     "nd_mlp_forward", "nd_mlp_grad", "nd_adam_step", "nd_last_error",
 )
@@ -46,7 +48,7 @@ class NDError(RuntimeError):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libnd.so is not built (%s); run `python -m paper_1905_09758_amd.build`" % LIB_PATH)
+    raise ImportError("libnd.so is not built (%s); run `python paper_1905_09758_amd/build.py`" % LIB_PATH)
 
 # torch first: libnd then binds to the HIP runtime torch has already loaded
 # (same soname), so device memory and streams are shared with torch's.
@@ -72,8 +74,9 @@ _sig("nd_graph_device_arrays", [_vp, _P(_vp), _P(_vp), _P(_vp)])
 _sig("nd_graph_step_timing", [_vp, _P(_dbl), _P(_i64)])
 _sig("nd_graph_free", [_vp], None)
 _sig("nd_motif_filter", [_vp, _u64, _u32, _vp, _P(_vp)])
-_sig("nd_motif_info", [_vp, _P(_i64), _P(_i64), _P(_i32), _P(_dbl), _P(_dbl)])
+_sig("nd_motif_info", [_vp, _P(_i64), _P(_i64), _P(_i32), _vp, _vp])
 _sig("nd_motif_export", [_vp, _vp, _vp])
+_sig("nd_motif_export_lambda", [_vp, _vp])
 _sig("nd_motifs_free", [_vp], None)
 _sig("nd_make_probes", [_vp, _vp, _i32, _u64, _u32, _vp, _vp])
 _sig("nd_cheb_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp])
@@ -226,10 +229,12 @@ def nd_motif_filter(g: Graph, seed: int, kinds: int = ND_TWINS_OPEN, stream=None
 
 def nd_motif_info(m: Motifs) -> dict:
     nc, nm, ns = _i64(), _i64(), _i32()
-    lam, w = _dbl(), _dbl()
-    _check(_lib.nd_motif_info(m.handle, ctypes.byref(nc), ctypes.byref(nm), ctypes.byref(ns), ctypes.byref(lam),
-                              ctypes.byref(w)), "nd_motif_info")
-    spikes = [(lam.value, w.value)] if ns.value else []
+    _check(_lib.nd_motif_info(m.handle, ctypes.byref(nc), ctypes.byref(nm), ctypes.byref(ns), None, None),
+           "nd_motif_info")
+    lam = np.empty(max(ns.value, 1), np.float64)
+    w = np.empty(max(ns.value, 1), np.float64)
+    _check(_lib.nd_motif_info(m.handle, None, None, None, lam.ctypes.data, w.ctypes.data), "nd_motif_info")
+    spikes = [(float(lam[i]), float(w[i])) for i in range(ns.value)]
     return {"n_classes": nc.value, "n_members": nm.value, "spikes": spikes}
 
 
@@ -238,6 +243,13 @@ def nd_motif_export(m: Motifs):
     mem = np.empty(max(m.n_members, 1), np.int32)
     _check(_lib.nd_motif_export(m.handle, ptr.ctypes.data, mem.ctypes.data), "nd_motif_export")
     return ptr, mem[:m.n_members]
+
+
+def nd_motif_export_lambda(m: Motifs) -> np.ndarray:
+    """Eigenvalue removed by each class: 0 (open twins) or -1/d (closed twins)."""
+    lam = np.empty(max(m.n_classes, 1), np.float64)
+    _check(_lib.nd_motif_export_lambda(m.handle, lam.ctypes.data), "nd_motif_export_lambda")
+    return lam[:m.n_classes]
 
 
 # ------------------------------------------------------------------ moments

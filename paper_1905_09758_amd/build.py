@@ -1,8 +1,9 @@
 """Build libnd.so (HIP, gfx950) in-tree from csrc/*.hip with hipcc.
 
 Each translation unit compiles to an object under _build/ (in parallel), then
-one shared library is linked next to this file.  Usable as
-``python -m paper_1905_09758_amd.build``.
+one shared library is linked next to this file.  Run it as a script,
+``python paper_1905_09758_amd/build.py`` (importing the package first would
+load the library it is about to rebuild).
 """
 from __future__ import annotations
 

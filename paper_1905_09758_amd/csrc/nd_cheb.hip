@@ -609,20 +609,36 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __rest
   }
 }
 
-// mu[m] = (1/k) sum_j mu_pp[j][m] + w T_m(0).
-__global__ __launch_bounds__(kBlock) void k_mu_final(const double* __restrict__ mu_pp, int k, int M, double w,
+// T_m(x) by the three-term recurrence (exact 1, 0, -1, 0, ... at x = 0).
+__device__ inline double cheb_T(int m, double x) {
+  double t0 = 1.0, t1 = x;
+  if (m == 0) return t0;
+  for (int i = 1; i < m; ++i) {
+    const double t2 = 2.0 * x * t1 - t0;
+    t0 = t1;
+    t1 = t2;
+  }
+  return t1;
+}
+
+// mu[m] = (1/k) sum_j mu_pp[j][m] + sum_s w_s T_m(lambda_s) over the removed
+// eigenvalues (spikes = lambdas then weights, n_spikes of each).
+__global__ __launch_bounds__(kBlock) void k_mu_final(const double* __restrict__ mu_pp, int k, int M,
+                                                     const double* __restrict__ spikes, int n_spikes,
                                                      double* __restrict__ mu) {
   for (int m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
     double sum = 0.0, comp = 0.0;
     for (int j = 0; j < k; ++j) neumaier(sum, comp, mu_pp[static_cast<int64_t>(j) * M + m]);
-    const double t0 = (m & 1) ? 0.0 : ((m & 2) ? -1.0 : 1.0);
-    mu[m] = (sum + comp) / static_cast<double>(k) + w * t0;
+    double add = 0.0;
+    for (int s = 0; s < n_spikes; ++s) add += spikes[n_spikes + s] * cheb_T(m, spikes[s]);
+    mu[m] = (sum + comp) / static_cast<double>(k) + add;
   }
 }
 
-// ldos[i][m] += (1 - 1/|C|) T_m(0) for every member i of a class C.
+// ldos[i][m] += (1 - 1/|C|) T_m(lambda_C) for every member i of a class C.
 __global__ __launch_bounds__(kBlock) void k_ldos_spike(const int64_t* __restrict__ class_ptr,
-                                                       const int32_t* __restrict__ members, int64_t n_classes,
+                                                       const int32_t* __restrict__ members,
+                                                       const double* __restrict__ class_lambda, int64_t n_classes,
                                                        int64_t n_members, int M, double* __restrict__ ldos) {
   for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n_members;
        p += static_cast<int64_t>(gridDim.x) * kBlock) {
@@ -632,8 +648,15 @@ __global__ __launch_bounds__(kBlock) void k_ldos_spike(const int64_t* __restrict
       if (class_ptr[mid] <= p) lo = mid; else hi = mid;
     }
     const double w = 1.0 - 1.0 / static_cast<double>(class_ptr[lo + 1] - class_ptr[lo]);
+    const double x = class_lambda[lo];
     double* row = ldos + static_cast<int64_t>(members[p]) * M;
-    for (int m = 0; m < M; m += 2) row[m] += (m & 2) ? -w : w;
+    double t0 = 1.0, t1 = x;
+    for (int m = 0; m < M; ++m) {
+      row[m] += w * t0;
+      const double t2 = 2.0 * x * t1 - t0;
+      t0 = t1;
+      t1 = t2;
+    }
   }
 }
 
@@ -717,7 +740,8 @@ struct MomentJob {
   double* ldos_sq = nullptr;
   double* mu = nullptr;
   double* mu_pp = nullptr;
-  double spike_w = 0.0;  // added to mu as w T_m(0)
+  const double* spikes = nullptr;  // device: removed eigenvalues, then their weights
+  int n_spikes = 0;                // (added to mu as sum_s w_s T_m(lambda_s))
   bool timed = false;
 };
 
@@ -904,14 +928,14 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     }
   }
   if (job.mu) {
-    hipLaunchKernelGGL(k_mu_final, dim3(grid_for(M, kBlock)), dim3(kBlock), 0, st, mu_pp, job.k, M, job.spike_w,
-                       job.mu);
+    hipLaunchKernelGGL(k_mu_final, dim3(grid_for(M, kBlock)), dim3(kBlock), 0, st, mu_pp, job.k, M, job.spikes,
+                       job.n_spikes, job.mu);
     ND_LAUNCH_CHECK();
   }
   if (job.ldos && job.motifs && job.motifs->n_classes > 0) {
     hipLaunchKernelGGL(k_ldos_spike, dim3(grid_for(job.motifs->n_members, kBlock)), dim3(kBlock), 0, st,
-                       job.motifs->class_ptr, job.motifs->members, job.motifs->n_classes, job.motifs->n_members, M,
-                       job.ldos);
+                       job.motifs->class_ptr, job.motifs->members, job.motifs->class_lambda, job.motifs->n_classes,
+                       job.motifs->n_members, M, job.ldos);
     ND_LAUNCH_CHECK();
   }
   return ND_OK;
@@ -1008,7 +1032,10 @@ nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
   job.ldos = ldos;
   job.ldos_sq = ldos_sq;
   job.mu = mu;
-  job.spike_w = motifs ? motifs->spike_weight : 0.0;
+  if (motifs) {
+    job.spikes = motifs->spikes_d;
+    job.n_spikes = static_cast<int>(motifs->spike_lambda.size());
+  }
   job.timed = (flags & ND_TIME_STEPS) != 0;
   nd_graph* gm = const_cast<nd_graph*>(g);
   if (flags & ND_STATE_FP64) return nd::run_moments<double>(gm, job, nd::as_stream(stream));

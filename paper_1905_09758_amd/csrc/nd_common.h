@@ -186,7 +186,10 @@ struct nd_motifs {
   int64_t n_classes = 0, n_members = 0;
   int64_t* class_ptr = nullptr;  // [n_classes+1]
   int32_t* members = nullptr;    // [n_members]
-  double spike_weight = 0.0;     // sum_C (|C|-1) / n
+  double* class_lambda = nullptr;  // [n_classes] eigenvalue removed by each class
+  // distinct removed eigenvalues (ascending) and their DOS mass sum (|C|-1)/n
+  std::vector<double> spike_lambda, spike_weight;
+  double* spikes_d = nullptr;    // device copy: lambdas then weights
   ~nd_motifs();
 };
 

@@ -1,15 +1,22 @@
-// Twin motifs (Sec. 3.4): nodes with identical open neighbourhoods.
+// Twin motifs (Sec. 3.4): nodes with identical open neighbourhoods
+// (eigenvalue 0 on the differences inside a class) or identical closed
+// neighbourhoods N(i) + {i} (adjacent nodes of equal degree d, eigenvalue
+// -1/d; the paper's blade motif at -1/2 and its -1/m family).
 //
 // The paper finds node copies with a random hash w = Hz and equal entries
 // w_i = w_j.  Here the hash is integer and order-free,
-//   h_i = sum_{j in N(i)} r_j  (mod 2^64),  r_j = SplitMix64 output j+1,
-// so it is identical on any thread mapping.  Nodes are sorted by h (stable,
-// ascending node id within equal keys); each run of equal h is a candidate
-// class, confirmed by exact comparison of the sorted neighbour lists against
-// the group leader.  Members that differ (hash collisions) are split off into
-// a new group led by their smallest member and verified again, until every
-// group is exact.  The resulting partition is independent of the seed.
+//   h_i = sum_{j in N(i)} r_j (+ r_i for closed neighbourhoods)  (mod 2^64),
+// r_j = SplitMix64 output j+1, so it is identical on any thread mapping.
+// Nodes are sorted by h (stable, ascending node id within equal keys); each
+// run of equal h is a candidate group, confirmed by exact comparison of the
+// sorted neighbour lists against the group leader.  Members that differ (hash
+// collisions) are split off into a new group led by their smallest member
+// and verified again, until every group is exact.  The partition is
+// independent of the seed.  A node cannot have twins of both kinds, so the
+// two passes give disjoint groups.
 #include <cstdlib>
+#include <map>
+#include <vector>
 
 #include "nd_common.h"
 
@@ -18,18 +25,18 @@ namespace {
 
 __global__ __launch_bounds__(kBlock) void k_twin_hash(const int64_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ col, int64_t n, uint64_t key,
-                                                      uint64_t mask, uint64_t* __restrict__ h,
+                                                      uint64_t mask, int closed, uint64_t* __restrict__ h,
                                                       uint32_t* __restrict__ idx) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    uint64_t s = 0;
+    uint64_t s = closed ? splitmix64(key, static_cast<uint64_t>(i) + 1) : 0;
     for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) s += splitmix64(key, static_cast<uint64_t>(col[e]) + 1);
     h[i] = s & mask;
     idx[i] = static_cast<uint32_t>(i);
   }
 }
 
-// label[p] = first position of p's run of equal hash; run_size at the head.
+// label[p] = first position of p's run of equal hash.
 __global__ __launch_bounds__(kBlock) void k_runs(const uint64_t* __restrict__ h, int64_t n,
                                                  int64_t* __restrict__ label) {
   for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
@@ -42,32 +49,52 @@ __global__ __launch_bounds__(kBlock) void k_runs(const uint64_t* __restrict__ h,
   }
 }
 
-__device__ inline bool same_neighbourhood(const int64_t* row_ptr, const int32_t* col, int64_t a, int64_t b) {
+// Open: N(a) == N(b).  Closed: a ~ b and N(a) - {b} == N(b) - {a} (sorted
+// lists compared while skipping b in a's list and a in b's list).
+__device__ inline bool same_neighbourhood(const int64_t* row_ptr, const int32_t* col, int64_t a, int64_t b,
+                                          bool closed) {
   const int64_t a0 = row_ptr[a], a1 = row_ptr[a + 1], b0 = row_ptr[b], b1 = row_ptr[b + 1];
   if (a1 - a0 != b1 - b0) return false;
-  for (int64_t t = 0; t < a1 - a0; ++t)
-    if (col[a0 + t] != col[b0 + t]) return false;
-  return true;
+  if (!closed) {
+    for (int64_t t = 0; t < a1 - a0; ++t)
+      if (col[a0 + t] != col[b0 + t]) return false;
+    return true;
+  }
+  bool adjacent = false;
+  int64_t i = a0, j = b0;
+  while (i < a1 || j < b1) {
+    if (i < a1 && col[i] == b) {
+      adjacent = true;
+      ++i;
+      continue;
+    }
+    if (j < b1 && col[j] == a) {
+      ++j;
+      continue;
+    }
+    if (i >= a1 || j >= b1 || col[i] != col[j]) return false;
+    ++i;
+    ++j;
+  }
+  return adjacent;
 }
 
 // Compare each non-leader with its group leader; mismatches propose the
 // smallest mismatching position of the group as the new group's leader.
 __global__ __launch_bounds__(kBlock) void k_verify(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                                    const uint32_t* __restrict__ node, const int64_t* __restrict__ label,
-                                                   int64_t n, int32_t* __restrict__ mism,
+                                                   int64_t n, int closed, int32_t* __restrict__ mism,
                                                    unsigned long long* __restrict__ newlab,
-                                                   unsigned long long* __restrict__ n_mism,
-                                                   int32_t* __restrict__ run_split, const int64_t* __restrict__ run_of) {
+                                                   unsigned long long* __restrict__ n_mism) {
   unsigned long long cnt = 0;
   for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
        p += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int64_t l = label[p];
     mism[p] = 0;
     if (l == p) continue;
-    if (!same_neighbourhood(row_ptr, col, node[p], node[l])) {
+    if (!same_neighbourhood(row_ptr, col, node[p], node[l], closed != 0)) {
       mism[p] = 1;
       atomicMin(&newlab[l], static_cast<unsigned long long>(p));
-      run_split[run_of[p]] = 1;
       cnt++;
     }
   }
@@ -90,21 +117,6 @@ __global__ __launch_bounds__(kBlock) void k_reset_newlab(int64_t n, unsigned lon
     newlab[p] = ~0ull;
 }
 
-// Run index of each position (run_of) from the initial labels.
-__global__ __launch_bounds__(kBlock) void k_run_flags(const int64_t* __restrict__ label, int64_t n,
-                                                      int32_t* __restrict__ flag) {
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
-       p += static_cast<int64_t>(gridDim.x) * kBlock)
-    flag[p] = label[p] == p ? 1 : 0;
-}
-
-__global__ __launch_bounds__(kBlock) void k_run_index(const int64_t* __restrict__ excl, const int32_t* __restrict__ flag,
-                                                      int64_t n, int64_t* __restrict__ run_of) {
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
-       p += static_cast<int64_t>(gridDim.x) * kBlock)
-    run_of[p] = excl[p] + flag[p] - 1;
-}
-
 // Group sizes (by leader position).
 __global__ __launch_bounds__(kBlock) void k_group_count(const int64_t* __restrict__ label, int64_t n,
                                                         int32_t* __restrict__ gsize) {
@@ -113,80 +125,77 @@ __global__ __launch_bounds__(kBlock) void k_group_count(const int64_t* __restric
     atomicAdd(&gsize[label[p]], 1);
 }
 
-// Mark the smallest member (the leader) of every group of size >= 2, by node id.
-__global__ __launch_bounds__(kBlock) void k_leader_flags(const int64_t* __restrict__ label,
-                                                         const int32_t* __restrict__ gsize,
-                                                         const uint32_t* __restrict__ node, int64_t n,
-                                                         int32_t* __restrict__ is_leader, int32_t* __restrict__ csize) {
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
-       p += static_cast<int64_t>(gridDim.x) * kBlock)
-    if (label[p] == p && gsize[p] >= 2) {
-      is_leader[node[p]] = 1;
-      csize[node[p]] = gsize[p];
-    }
-}
-
-// Class size indexed by class (ordered by leader node id).
-__global__ __launch_bounds__(kBlock) void k_class_sizes(const int32_t* __restrict__ is_leader,
-                                                        const int32_t* __restrict__ csize,
-                                                        const int64_t* __restrict__ cls_of_node, int64_t n,
-                                                        int64_t* __restrict__ sizes) {
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kBlock)
-    if (is_leader[i]) sizes[cls_of_node[i]] = csize[i];
-}
-
-// Rank of each member inside its group, in ascending position (= node) order.
-// Runs that never split hold one group in consecutive positions.
-__global__ __launch_bounds__(kBlock) void k_rank_simple(const int64_t* __restrict__ label,
-                                                        const int32_t* __restrict__ run_split,
-                                                        const int64_t* __restrict__ run_of, int64_t n,
-                                                        int64_t* __restrict__ rank) {
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
-       p += static_cast<int64_t>(gridDim.x) * kBlock)
-    if (!run_split[run_of[p]]) rank[p] = p - label[p];
-}
-
-// Split runs: one thread walks the run and counts per group (by leader position).
-__global__ __launch_bounds__(kBlock) void k_rank_split(const int64_t* __restrict__ label,
-                                                       const int32_t* __restrict__ run_split,
-                                                       const int64_t* __restrict__ run_of, int64_t n,
-                                                       int32_t* __restrict__ counter, int64_t* __restrict__ rank) {
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
-       p += static_cast<int64_t>(gridDim.x) * kBlock) {
-    if (!(p == 0 || run_of[p] != run_of[p - 1])) continue;  // run heads only
-    if (!run_split[run_of[p]]) continue;
-    for (int64_t t = p; t < n && run_of[t] == run_of[p]; ++t) rank[t] = counter[label[t]]++;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_scatter_members(const int64_t* __restrict__ label,
-                                                            const int32_t* __restrict__ gsize,
-                                                            const uint32_t* __restrict__ node,
-                                                            const int64_t* __restrict__ cls_of_node,
-                                                            const int64_t* __restrict__ class_ptr,
-                                                            const int64_t* __restrict__ rank, int64_t n,
-                                                            int32_t* __restrict__ members) {
+// Per node: the smallest node of its group (the leader position holds it:
+// positions of a run are in ascending node order and split groups are led by
+// their smallest position), or -1 for groups of one.
+__global__ __launch_bounds__(kBlock) void k_node_labels(const int64_t* __restrict__ label,
+                                                        const int32_t* __restrict__ gsize,
+                                                        const uint32_t* __restrict__ node, int64_t n,
+                                                        int32_t* __restrict__ lab) {
   for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
        p += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int64_t l = label[p];
-    if (gsize[l] < 2) continue;
-    const int64_t c = cls_of_node[node[l]];
-    members[class_ptr[c] + rank[p]] = static_cast<int32_t>(node[p]);
+    lab[node[p]] = gsize[l] >= 2 ? static_cast<int32_t>(node[l]) : -1;
   }
 }
 
-
-nd_status twins_impl(const nd_graph* g, uint64_t seed, hipStream_t st, nd_motifs* out) {
-  const int64_t n = g->n;
-  out->n = n;
-  if (n < 2) {
-    ND_CHECK(dalloc_t(&out->class_ptr, 1));
-    ND_HIP(hipMemsetAsync(out->class_ptr, 0, 8, st));
-    ND_HIP(hipStreamSynchronize(st));
-    return ND_OK;
+// Merge the closed-neighbourhood labels into the open ones (disjoint).
+__global__ __launch_bounds__(kBlock) void k_merge_labels(int32_t* __restrict__ lab, const int32_t* __restrict__ lab2,
+                                                         int64_t n, int32_t* __restrict__ closed_flag) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    if (lab[i] < 0 && lab2[i] >= 0) {
+      lab[i] = lab2[i];
+      closed_flag[i] = 1;
+    }
   }
-  Tmp t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_leaders(const int32_t* __restrict__ lab, int64_t n,
+                                                    int32_t* __restrict__ is_leader, int32_t* __restrict__ cnt) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int32_t l = lab[i];
+    is_leader[i] = (l == i) ? 1 : 0;
+    if (l >= 0) atomicAdd(&cnt[l], 1);
+  }
+}
+
+// Class c (classes ordered by leader node): size and removed eigenvalue
+// (0 for open twins, -1/d for closed twins of degree d).
+__global__ __launch_bounds__(kBlock) void k_class_info(const int32_t* __restrict__ is_leader,
+                                                       const int32_t* __restrict__ cnt,
+                                                       const int64_t* __restrict__ cls_of_node,
+                                                       const int32_t* __restrict__ closed_flag,
+                                                       const int64_t* __restrict__ row_ptr, int64_t n,
+                                                       int64_t* __restrict__ sizes, double* __restrict__ lam) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    if (!is_leader[i]) continue;
+    const int64_t c = cls_of_node[i];
+    sizes[c] = cnt[i];
+    lam[c] = closed_flag[i] ? -1.0 / static_cast<double>(row_ptr[i + 1] - row_ptr[i]) : 0.0;
+  }
+}
+
+// Sort keys: the class of each member (n_cls for nodes outside the classes),
+// node ids as payload; a stable sort then lists every class's members in
+// ascending order, classes in leader order.
+__global__ __launch_bounds__(kBlock) void k_member_keys(const int32_t* __restrict__ lab,
+                                                        const int64_t* __restrict__ cls_of_node, int64_t n,
+                                                        int64_t n_cls, uint64_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ vals) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int32_t l = lab[i];
+    keys[i] = static_cast<uint64_t>(l >= 0 ? cls_of_node[l] : n_cls);
+    vals[i] = static_cast<uint32_t>(i);
+  }
+}
+
+// One detection pass: lab[i] = leader node of i's exact group (size >= 2) or -1.
+nd_status twin_pass(const nd_graph* g, uint64_t seed, bool closed, hipStream_t st, Tmp& t, int32_t* lab) {
+  const int64_t n = g->n;
   const int grid = grid_for(n, kBlock);
   uint64_t *h, *h2;
   uint32_t *node, *node2;
@@ -200,37 +209,27 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, hipStream_t st, nd_motifs
     if (b > 0 && b < 64) mask = (1ull << b) - 1ull;
   }
   hipLaunchKernelGGL(k_twin_hash, dim3(grid), dim3(kBlock), 0, st, g->row_ptr, g->col, n, splitmix64(seed, 1), mask,
-                     h, node);
+                     closed ? 1 : 0, h, node);
   ND_LAUNCH_CHECK();
   ND_CHECK(radix_sort_u64(h, h2, node, node2, n, 64, st));
-  int64_t *label, *run_of, *excl, *tot;
-  int32_t *flag, *mism, *run_split;
+  int64_t* label;
+  int32_t *mism, *gsize;
   unsigned long long *newlab, *n_mism;
   ND_CHECK(t.get(&label, n));
-  ND_CHECK(t.get(&run_of, n));
-  ND_CHECK(t.get(&excl, n));
-  ND_CHECK(t.get(&tot, 1));
-  ND_CHECK(t.get(&flag, n));
   ND_CHECK(t.get(&mism, n));
-  ND_CHECK(t.get(&run_split, n));
+  ND_CHECK(t.get(&gsize, n));
   ND_CHECK(t.get(&newlab, n));
   ND_CHECK(t.get(&n_mism, 1));
   hipLaunchKernelGGL(k_runs, dim3(grid), dim3(kBlock), 0, st, h, n, label);
   ND_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_run_flags, dim3(grid), dim3(kBlock), 0, st, label, n, flag);
-  ND_LAUNCH_CHECK();
-  ND_CHECK(exclusive_scan_i32_i64(flag, excl, n, tot, st));
-  hipLaunchKernelGGL(k_run_index, dim3(grid), dim3(kBlock), 0, st, excl, flag, n, run_of);
-  ND_LAUNCH_CHECK();
-  ND_HIP(hipMemsetAsync(run_split, 0, static_cast<size_t>(n) * 4, st));
   hipLaunchKernelGGL(k_reset_newlab, dim3(grid), dim3(kBlock), 0, st, n, newlab);
   ND_LAUNCH_CHECK();
   // every iteration splits at least one new exact group off each mixed group,
   // so n iterations always suffice
   for (int64_t iter = 0; iter < n; ++iter) {
     ND_HIP(hipMemsetAsync(n_mism, 0, 8, st));
-    hipLaunchKernelGGL(k_verify, dim3(grid), dim3(kBlock), 0, st, g->row_ptr, g->col, node, label, n, mism, newlab,
-                       n_mism, run_split, run_of);
+    hipLaunchKernelGGL(k_verify, dim3(grid), dim3(kBlock), 0, st, g->row_ptr, g->col, node, label, n,
+                       closed ? 1 : 0, mism, newlab, n_mism);
     ND_LAUNCH_CHECK();
     unsigned long long hm = 0;
     ND_HIP(hipMemcpyAsync(&hm, n_mism, 8, hipMemcpyDeviceToHost, st));
@@ -241,18 +240,55 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, hipStream_t st, nd_motifs
     hipLaunchKernelGGL(k_reset_newlab, dim3(grid), dim3(kBlock), 0, st, n, newlab);
     ND_LAUNCH_CHECK();
   }
-  int32_t *gsize, *is_leader, *csize;
-  int64_t *cls_of_node, *sizes, *rank;
-  ND_CHECK(t.get(&gsize, n));
-  ND_CHECK(t.get(&is_leader, n));
-  ND_CHECK(t.get(&csize, n));
-  ND_CHECK(t.get(&cls_of_node, n));
-  ND_CHECK(t.get(&rank, n));
   ND_HIP(hipMemsetAsync(gsize, 0, static_cast<size_t>(n) * 4, st));
-  ND_HIP(hipMemsetAsync(is_leader, 0, static_cast<size_t>(n) * 4, st));
   hipLaunchKernelGGL(k_group_count, dim3(grid), dim3(kBlock), 0, st, label, n, gsize);
   ND_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_leader_flags, dim3(grid), dim3(kBlock), 0, st, label, gsize, node, n, is_leader, csize);
+  hipLaunchKernelGGL(k_node_labels, dim3(grid), dim3(kBlock), 0, st, label, gsize, node, n, lab);
+  ND_LAUNCH_CHECK();
+  return ND_OK;
+}
+
+nd_status twins_impl(const nd_graph* g, uint64_t seed, uint32_t kinds, hipStream_t st, nd_motifs* out) {
+  const int64_t n = g->n;
+  out->n = n;
+  if (n < 2) {
+    ND_CHECK(dalloc_t(&out->class_ptr, 1));
+    ND_HIP(hipMemsetAsync(out->class_ptr, 0, 8, st));
+    ND_HIP(hipStreamSynchronize(st));
+    return ND_OK;
+  }
+  Tmp t;
+  const int grid = grid_for(n, kBlock);
+  int32_t *lab, *closed_flag;
+  ND_CHECK(t.get(&lab, n));
+  ND_CHECK(t.get(&closed_flag, n));
+  ND_HIP(hipMemsetAsync(closed_flag, 0, static_cast<size_t>(n) * 4, st));
+  if (kinds & ND_TWINS_OPEN) {
+    ND_CHECK(twin_pass(g, seed, false, st, t, lab));
+    if (kinds & ND_TWINS_CLOSED) {
+      int32_t* lab2;
+      ND_CHECK(t.get(&lab2, n));
+      ND_CHECK(twin_pass(g, seed, true, st, t, lab2));
+      hipLaunchKernelGGL(k_merge_labels, dim3(grid), dim3(kBlock), 0, st, lab, lab2, n, closed_flag);
+      ND_LAUNCH_CHECK();
+    }
+  } else {
+    // closed only: every labelled node is a closed twin
+    int32_t* lab0;
+    ND_CHECK(t.get(&lab0, n));
+    ND_HIP(hipMemsetAsync(lab, 0xFF, static_cast<size_t>(n) * 4, st));
+    ND_CHECK(twin_pass(g, seed, true, st, t, lab0));
+    hipLaunchKernelGGL(k_merge_labels, dim3(grid), dim3(kBlock), 0, st, lab, lab0, n, closed_flag);
+    ND_LAUNCH_CHECK();
+  }
+  int32_t *is_leader, *cnt;
+  int64_t *cls_of_node, *tot;
+  ND_CHECK(t.get(&is_leader, n));
+  ND_CHECK(t.get(&cnt, n));
+  ND_CHECK(t.get(&cls_of_node, n));
+  ND_CHECK(t.get(&tot, 1));
+  ND_HIP(hipMemsetAsync(cnt, 0, static_cast<size_t>(n) * 4, st));
+  hipLaunchKernelGGL(k_leaders, dim3(grid), dim3(kBlock), 0, st, lab, n, is_leader, cnt);
   ND_LAUNCH_CHECK();
   ND_CHECK(exclusive_scan_i32_i64(is_leader, cls_of_node, n, tot, st));
   int64_t n_cls = 0;
@@ -265,28 +301,47 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, hipStream_t st, nd_motifs
     ND_HIP(hipStreamSynchronize(st));
     return ND_OK;
   }
+  int64_t* sizes;
   ND_CHECK(t.get(&sizes, n_cls));
-  hipLaunchKernelGGL(k_class_sizes, dim3(grid), dim3(kBlock), 0, st, is_leader, csize, cls_of_node, n, sizes);
+  ND_CHECK(dalloc_t(&out->class_lambda, static_cast<size_t>(n_cls)));
+  hipLaunchKernelGGL(k_class_info, dim3(grid), dim3(kBlock), 0, st, is_leader, cnt, cls_of_node, closed_flag,
+                     g->row_ptr, n, sizes, out->class_lambda);
   ND_LAUNCH_CHECK();
   ND_CHECK(exclusive_scan_i64(sizes, out->class_ptr, n_cls, tot, st));
   ND_HIP(hipMemcpyAsync(out->class_ptr + n_cls, tot, 8, hipMemcpyDeviceToDevice, st));
   int64_t n_mem = 0;
   ND_HIP(hipMemcpyAsync(&n_mem, tot, 8, hipMemcpyDeviceToHost, st));
+  // spikes: total (|C| - 1) per distinct eigenvalue, ascending
+  std::vector<int64_t> h_sizes(static_cast<size_t>(n_cls));
+  std::vector<double> h_lam(static_cast<size_t>(n_cls));
+  ND_HIP(hipMemcpyAsync(h_sizes.data(), sizes, static_cast<size_t>(n_cls) * 8, hipMemcpyDeviceToHost, st));
+  ND_HIP(hipMemcpyAsync(h_lam.data(), out->class_lambda, static_cast<size_t>(n_cls) * 8, hipMemcpyDeviceToHost, st));
   ND_HIP(hipStreamSynchronize(st));
   out->n_members = n_mem;
-  out->spike_weight = static_cast<double>(n_mem - n_cls) / static_cast<double>(n);
+  std::map<double, int64_t> acc;
+  for (int64_t c = 0; c < n_cls; ++c) acc[h_lam[c]] += h_sizes[c] - 1;
+  for (const auto& kv : acc) {
+    out->spike_lambda.push_back(kv.first);
+    out->spike_weight.push_back(static_cast<double>(kv.second) / static_cast<double>(n));
+  }
+  const size_t ns = out->spike_lambda.size();
+  ND_CHECK(dalloc_t(&out->spikes_d, 2 * ns));
+  ND_HIP(hipMemcpyAsync(out->spikes_d, out->spike_lambda.data(), ns * 8, hipMemcpyHostToDevice, st));
+  ND_HIP(hipMemcpyAsync(out->spikes_d + ns, out->spike_weight.data(), ns * 8, hipMemcpyHostToDevice, st));
+  // members: stable sort of the nodes by class
+  uint64_t *keys, *keys2;
+  uint32_t *vals, *vals2;
+  ND_CHECK(t.get(&keys, n));
+  ND_CHECK(t.get(&keys2, n));
+  ND_CHECK(t.get(&vals, n));
+  ND_CHECK(t.get(&vals2, n));
+  hipLaunchKernelGGL(k_member_keys, dim3(grid), dim3(kBlock), 0, st, lab, cls_of_node, n, n_cls, keys, vals);
+  ND_LAUNCH_CHECK();
+  int nbits = 0;
+  while ((uint64_t(1) << nbits) <= static_cast<uint64_t>(n_cls)) ++nbits;
+  ND_CHECK(radix_sort_u64(keys, keys2, vals, vals2, n, nbits, st));
   ND_CHECK(dalloc_t(&out->members, static_cast<size_t>(n_mem)));
-  // ranks: reuse gsize-shaped counters for split runs
-  int32_t* counter;
-  ND_CHECK(t.get(&counter, n));
-  ND_HIP(hipMemsetAsync(counter, 0, static_cast<size_t>(n) * 4, st));
-  hipLaunchKernelGGL(k_rank_simple, dim3(grid), dim3(kBlock), 0, st, label, run_split, run_of, n, rank);
-  ND_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_rank_split, dim3(grid), dim3(kBlock), 0, st, label, run_split, run_of, n, counter, rank);
-  ND_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_scatter_members, dim3(grid), dim3(kBlock), 0, st, label, gsize, node, cls_of_node,
-                     out->class_ptr, rank, n, out->members);
-  ND_LAUNCH_CHECK();
+  ND_HIP(hipMemcpyAsync(out->members, vals, static_cast<size_t>(n_mem) * 4, hipMemcpyDeviceToDevice, st));
   ND_HIP(hipStreamSynchronize(st));
   return ND_OK;
 }
@@ -297,6 +352,8 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, hipStream_t st, nd_motifs
 nd_motifs::~nd_motifs() {
   nd::dfree(class_ptr);
   nd::dfree(members);
+  nd::dfree(class_lambda);
+  nd::dfree(spikes_d);
 }
 
 extern "C" {
@@ -306,13 +363,13 @@ nd_status nd_motif_filter(const nd_graph* g, uint64_t seed, uint32_t kinds, void
   ND_REQUIRE(out != nullptr, "nd_motif_filter: out is NULL");
   *out = nullptr;
   ND_REQUIRE(g != nullptr, "nd_motif_filter: graph is NULL");
-  if (kinds != ND_TWINS_OPEN) {
-    nd::set_error("nd_motif_filter: kinds=0x%x; only ND_TWINS_OPEN is implemented", kinds);
+  if (kinds == 0 || (kinds & ~(ND_TWINS_OPEN | ND_TWINS_CLOSED)) != 0) {
+    nd::set_error("nd_motif_filter: kinds=0x%x; implemented: ND_TWINS_OPEN, ND_TWINS_CLOSED", kinds);
     return ND_EUNSUPPORTED;
   }
   std::unique_ptr<nd_motifs> m(new nd_motifs());
   ND_HIP(hipGetDevice(&m->device));
-  ND_CHECK(nd::twins_impl(g, seed, nd::as_stream(stream), m.get()));
+  ND_CHECK(nd::twins_impl(g, seed, kinds, nd::as_stream(stream), m.get()));
   *out = m.release();
   return ND_OK;
 }
@@ -323,10 +380,12 @@ nd_status nd_motif_info(const nd_motifs* m, int64_t* n_classes, int64_t* n_motif
   ND_REQUIRE(m != nullptr, "nd_motif_info: motifs is NULL");
   if (n_classes) *n_classes = m->n_classes;
   if (n_motif_nodes) *n_motif_nodes = m->n_members;
-  const int32_t ns = m->n_classes > 0 ? 1 : 0;
-  if (n_spikes) *n_spikes = ns;
-  if (ns && spike_lambda) spike_lambda[0] = 0.0;
-  if (ns && spike_weight) spike_weight[0] = m->spike_weight;
+  const size_t ns = m->spike_lambda.size();
+  if (n_spikes) *n_spikes = static_cast<int32_t>(ns);
+  for (size_t s = 0; s < ns; ++s) {
+    if (spike_lambda) spike_lambda[s] = m->spike_lambda[s];
+    if (spike_weight) spike_weight[s] = m->spike_weight[s];
+  }
   return ND_OK;
 }
 
@@ -338,6 +397,15 @@ nd_status nd_motif_export(const nd_motifs* m, int64_t* class_ptr, int32_t* membe
     ND_HIP(hipMemcpy(class_ptr, m->class_ptr, static_cast<size_t>(m->n_classes + 1) * 8, hipMemcpyDeviceToHost));
   if (members && m->n_members)
     ND_HIP(hipMemcpy(members, m->members, static_cast<size_t>(m->n_members) * 4, hipMemcpyDeviceToHost));
+  return ND_OK;
+}
+
+nd_status nd_motif_export_lambda(const nd_motifs* m, double* class_lambda) {
+  nd::clear_error();
+  ND_REQUIRE(m != nullptr && class_lambda != nullptr, "nd_motif_export_lambda: NULL argument");
+  ND_HIP(hipDeviceSynchronize());
+  if (m->n_classes)
+    ND_HIP(hipMemcpy(class_lambda, m->class_lambda, static_cast<size_t>(m->n_classes) * 8, hipMemcpyDeviceToHost));
   return ND_OK;
 }
 

@@ -195,7 +195,7 @@ extern "C" nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_
   ND_REQUIRE(!rho || (n_points >= 1 && n_points <= 4096), "nd_reconstruct: n_points=%d not in [1, 4096]",
              n_points);
   ND_REQUIRE(!hist || (lo >= -1.0 && hi <= 1.0 && lo < hi), "nd_reconstruct: need -1 <= lo < hi <= 1");
-  ND_REQUIRE(n_spikes >= 0 && n_spikes <= 64, "nd_reconstruct: n_spikes=%d not in [0, 64]", n_spikes);
+  ND_REQUIRE(n_spikes >= 0 && n_spikes <= 1024, "nd_reconstruct: n_spikes=%d not in [0, 1024]", n_spikes);
   ND_REQUIRE(n_spikes == 0 || (spike_lambda && spike_weight), "nd_reconstruct: spike arrays are NULL");
   hipStream_t st = as_stream(stream);
   const int nb = hist ? n_bins : 0, np = rho ? n_points : 0;

@@ -100,6 +100,86 @@ def test_twins_bit_exact(case, nd):
         assert m.spikes[0][1] == pytest.approx(twins.spike_weight(cls, g_or.n), rel=0, abs=1e-15)
 
 
+def _mixed_twins():
+    n, s, d = sg.barabasi_albert(2000, 2, seed=8, twin_pairs=30)
+    return sg.plant_adjacent_pairs(n, s, d, 45, seed=9)
+
+
+TWIN_GRAPHS = {
+    "mixed": _mixed_twins,
+    "friendship": lambda: sg.friendship(40),
+    "complete": lambda: sg.complete(9),
+    "rmat10": lambda: sg.rmat(10, 4, seed=2),
+}
+KINDS = {"open": 0x1, "closed": 0x2, "both": 0x3}
+
+
+def _check_classes(nd, m, g_or, kind):
+    ptr, mem = nd.nd_motif_export(m)
+    cls = twins.twin_classes(g_or, kind)
+    p2, m2 = twins.classes_to_arrays(cls)
+    assert np.array_equal(ptr, p2) and np.array_equal(mem, m2)
+    lam = [twins.class_eigenvalue(g_or, c) for c in cls]
+    assert nd.nd_motif_export_lambda(m).tolist() == lam
+    assert m.spikes == twins.spikes(cls, lam, g_or.n)
+    return cls, lam
+
+
+@pytest.mark.parametrize("gname", sorted(TWIN_GRAPHS))
+@pytest.mark.parametrize("kind", sorted(KINDS))
+def test_twin_kinds_bit_exact(nd, gname, kind):
+    n, s, d = TWIN_GRAPHS[gname]()
+    g_or = og.build_csr(n, s, d)
+    g = nd.nd_build_csr(n, s, d)
+    m = nd.nd_motif_filter(g, 7, KINDS[kind])
+    cls, lam = _check_classes(nd, m, g_or, kind)
+    if gname == "mixed" and kind == "both":
+        assert 0.0 in lam and -0.5 in lam and -1.0 / 3.0 in lam and -0.25 in lam
+
+
+def test_twins_under_forced_hash_collisions(nd, monkeypatch):
+    """With the hash cut to 3 bits nearly every node collides: the exact
+    verification must still split the candidate groups into the true classes."""
+    n, s, d = _mixed_twins()
+    g_or = og.build_csr(n, s, d)
+    g = nd.nd_build_csr(n, s, d)
+    monkeypatch.setenv("ND_TWIN_HASH_BITS", "3")
+    for kind in ("open", "closed", "both"):
+        m = nd.nd_motif_filter(g, 11, KINDS[kind])
+        _check_classes(nd, m, g_or, kind)
+
+
+def test_filtered_moments_both_kinds(nd):
+    """Probes projected over open and closed classes; per-node rows get back
+    (1 - 1/|C|) T_m(lambda_C) and mu the spikes sum_s w_s T_m(lambda_s)."""
+    import torch
+    n, s, d = _mixed_twins()
+    g_or = og.build_csr(n, s, d)
+    g = nd.nd_build_csr(n, s, d)
+    m = nd.nd_motif_filter(g, 5, KINDS["both"])
+    cls = twins.twin_classes(g_or, "both")
+    lam = [twins.class_eigenvalue(g_or, c) for c in cls]
+    k, M = 24, 90
+    H = og.normalized_adjacency(g_or)
+    Z = orng.rademacher(g_or.n, k, 31)
+    mu_full, mu_s, mupp_s, C = twins.filtered_moments(H, Z, M, cls, lambdas=lam)
+    mu = _zeros(M, torch.float64)
+    mupp = _zeros(k * M, torch.float64)
+    nd.nd_cheb_moments(g, m, k, M, 31, 0, mu, mupp)
+    assert np.max(np.abs(mu.cpu().numpy() - mu_s)) < TOL_MU
+    assert np.max(np.abs(mupp.cpu().numpy().reshape(k, M) - mupp_s)) < TOL_MU
+    ld = _zeros(g.n * M, torch.float64)
+    mu2 = _zeros(M, torch.float64)
+    nd.nd_ldos_moments(g, m, k, M, 31, 0, ld, mu=mu2)
+    assert np.max(np.abs(ld.cpu().numpy().reshape(g.n, M) - C)) < 1e-5
+    assert np.max(np.abs(mu2.cpu().numpy() - mu_full)) < TOL_MU
+    # the smooth moments plus the spikes reconstruct the full histogram
+    hist = _zeros(100, torch.float64)
+    nd.nd_reconstruct(mu2, 1, M, nd.ND_KERNEL_JACKSON | nd.ND_SPIKES_IN_MOMENTS, m.spikes, 100, -1.0, 1.0, hist)
+    h_o = rc.histogram(mu_s, 100, kernel="jackson", spikes=twins.spikes(cls, lam, g_or.n))
+    assert np.abs(hist.cpu().numpy() - h_o).sum() < 1e-3
+
+
 @pytest.mark.parametrize("k,M", [(20, 100), (64, 60), (3, 200), (100, 30)])
 def test_global_moments(case, nd, k, M):
     import torch
@@ -288,9 +368,10 @@ def test_errors(nd):
         nd.nd_build_csr(3, np.array([0, 1], np.int32), np.array([1, 5], np.int32))
     assert e.value.status == nd.ND_EINVAL
     g = nd.nd_build_csr(4, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
-    with pytest.raises(nd.NDError) as e:
-        nd.nd_motif_filter(g, 1, kinds=0x4)
-    assert e.value.status == nd.ND_EUNSUPPORTED
+    for bad in (0x4, 0x0, 0x5):
+        with pytest.raises(nd.NDError) as e:
+            nd.nd_motif_filter(g, 1, kinds=bad)
+        assert e.value.status == nd.ND_EUNSUPPORTED
     mu = _zeros(4, torch.float64)
     with pytest.raises(nd.NDError):
         nd.nd_cheb_moments(g, None, 0, 4, 1, 0, mu)
