@@ -67,6 +67,9 @@ typedef struct nd_motifs nd_motifs; /* twin classes found in a graph */
 #define ND_TIME_STEPS 0x4u        /* time each sparse-product step launch with HIP events
                                      (read back with nd_graph_step_timing; adds a
                                      host synchronisation at the end of the call) */
+#define ND_MOMENT_DOUBLING 0x8u   /* nd_cheb_moments only: moments 2s-1 and 2s from
+                                     Y_s.Y_{s-1} and Y_s.Y_s (floor(M/2) sparse
+                                     products instead of M-1) */
 
 #define ND_TWINS_OPEN 0x1u        /* nd_motif_filter: nodes with equal open neighbourhoods */
 #define ND_TWINS_CLOSED 0x2u      /* nd_motif_filter: adjacent nodes with equal closed
@@ -175,7 +178,14 @@ nd_status nd_make_probes(const nd_graph* g, const nd_motifs* motifs, int32_t n_p
  * three-term recurrence (eq. cheb_3term) applied to the whole probe block.
  *   n_probes >= 1 (any count; blocks of up to 64 run one after another)
  *   n_moments >= 1
- *   flags    ND_PROBE_RADEMACHER | ND_PROBE_GAUSSIAN, optionally ND_STATE_FP64
+ *   flags    ND_PROBE_RADEMACHER | ND_PROBE_GAUSSIAN, optionally ND_STATE_FP64,
+ *            ND_TIME_STEPS, ND_MOMENT_DOUBLING.  With ND_MOMENT_DOUBLING the
+ *            same estimates come from floor(M/2) products through the
+ *            identities T_s T_{s-1} = (T_{2s-1} + T_1)/2 and
+ *            T_s^2 = (T_{2s} + T_0)/2 (the cited KPM review's doubling trick):
+ *              mu_pp[j][2s]   = (2/N) y_s.y_s - mu_pp[j][0],
+ *              mu_pp[j][2s-1] = (2/N) y_s.y_{s-1} - mu_pp[j][1],
+ *            y_s = T_s(H) z_j; equal to the direct sums in exact arithmetic.
  *   motifs   NULL, or twin classes to filter: the probes are projected and
  *            mu/mu_pp hold the moments of the remaining (smooth) spectrum;
  *            the full-DOS moments are mu[m] + sum_s w_s T_m(lambda_s) over

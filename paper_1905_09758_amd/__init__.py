@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libnd.so")
 ND_OK, ND_EINVAL, ND_ENOMEM, ND_EDEVICE, ND_EOVERFLOW, ND_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ND_INPUT_DEVICE = 0x1
 ND_PROBE_RADEMACHER, ND_PROBE_GAUSSIAN, ND_STATE_FP64, ND_TIME_STEPS = 0x0, 0x1, 0x2, 0x4
+ND_MOMENT_DOUBLING = 0x8
 ND_TWINS_OPEN = 0x1
 ND_TWINS_CLOSED = 0x2
 ND_KERNEL_NONE, ND_KERNEL_JACKSON, ND_SPIKES_IN_MOMENTS = 0, 1, 0x10

@@ -121,7 +121,8 @@ struct StepArgs {
   int64_t chunk_nnz;
   int64_t n_split;         // split rows are internal rows [0, n_split)
   int slot_nnz;            // nonzeros per slot and gather batch (4 or 8)
-  int zmode;               // 0: probe rows read from z; 1: Rademacher rows regenerated
+  int zmode;               // 0: probe rows read from z; 1: Rademacher rows regenerated;
+                           // 2: doubling steps (products of Y_m with Y_m and Y_{m-1}, no probes)
   uint64_t seed;           // probe seed and index of this block's first probe (zmode 1)
   int64_t j0;
   const int32_t* zcls;     // zmode 1 with twin filtering: class of each internal row or -1
@@ -135,7 +136,7 @@ struct StepArgs {
   int k_batch;      // real probes in this block
   double inv_k;     // 1 / (total probe count over all blocks)
   int m;            // moment index written by this launch
-  double* partial;  // [step grid + split_blocks][kp] per-probe partial sums for moment m
+  double* partial;  // [step grid + split_blocks][sums][kp] per-probe partial sums of launch m
   int split_blocks; // grid of the split-row finisher; its slots follow the step kernel's
   double* ldos;     // [n][ld] (compact node order) or null
   double* ldos_sq;  // [n][ld] or null
@@ -143,6 +144,11 @@ struct StepArgs {
   int accumulate;   // add to ldos instead of overwriting (later probe blocks)
   const float* cv_g;
 };
+
+// Per-probe sums a row epilogue produces: z.Y_m (probe modes), or the two
+// products Y_m.Y_{m-1} and Y_m.Y_m of the doubling steps.
+template <int ZM>
+constexpr int kSums = ZM == 2 ? 2 : 1;
 
 // Per-row epilogue: given Y_m(i, probes of this lane) in fp64 and the probe
 // values z, form the estimator terms v_ij = z_ij y_ij (+ g_im (1 - z_ij^2)
@@ -186,12 +192,14 @@ __device__ inline void emit_moments(const StepArgs& a, bool own, int64_t node, c
 }
 
 // The per-row operands that do not depend on the gathers: X_{m-1}(r), the
-// node id and, when probe rows are read (ZM == 0), the probe values.  Issued
-// before the gathers so that their latency overlaps with them.
+// node id and, when probe rows are read (ZM == 0), the probe values; in the
+// doubling steps (ZM == 2) the row's own entry of the gathered block X_m.
+// Issued before the gathers so that their latency overlaps with them.
 template <typename T, int ZM>
 struct RowOperands {
   T xp[16 / sizeof(T)];
   T z[ZM == 0 ? 16 / sizeof(T) : 1];
+  T xo[ZM == 2 ? 16 / sizeof(T) : 1];
   int64_t node;
 };
 
@@ -205,10 +213,17 @@ __device__ inline void load_row_operands(const StepArgs& a, bool own, int64_t r,
 #pragma unroll
     for (int c = 0; c < PPL; ++c) o.z[c] = T(0);
   }
+  if constexpr (ZM == 2) {
+#pragma unroll
+    for (int c = 0; c < PPL; ++c) o.xo[c] = T(0);
+  }
   if (own) {
     if (!a.first) load16_nt<T>(reinterpret_cast<const T*>(a.xio) + r * a.kp + q * PPL, o.xp);
-    if (ZM == 1 || a.ldos || a.cv_g) o.node = a.perm[r];
+    if constexpr (ZM != 2) {
+      if (ZM == 1 || a.ldos || a.cv_g) o.node = a.perm[r];
+    }
     if constexpr (ZM == 0) load16_nt<T>(reinterpret_cast<const T*>(a.z) + r * a.kp + q * PPL, o.z);
+    if constexpr (ZM == 2) load16<T>(reinterpret_cast<const T*>(a.xg) + r * a.kp + q * PPL, o.xo);
   }
 }
 
@@ -241,7 +256,9 @@ __device__ inline void row_probes(const StepArgs& a, bool own, int64_t r, int q,
 
 // Finish row r: X_{m+1} = 2/d * acc - X_{m-1} (or acc/d on the first step)
 // evaluated in the accumulator type A, stored in place, then the moment
-// epilogue on Y = sqrt(d) X.
+// epilogue on Y = sqrt(d) X.  Doubling steps add Y_{m+1}.Y_m and
+// Y_{m+1}.Y_{m+1} per probe instead (T_{m+1} T_m = (T_{2m+1} + T_1)/2 and
+// T_{m+1}^2 = (T_{2m+2} + T_0)/2 turn them into two moments each).
 template <typename T, int L, int ZM, typename A>
 __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_t d, const A (&acc)[16 / sizeof(T)],
                                   const RowOperands<T, ZM>& o, int q, double* mom) {
@@ -267,9 +284,22 @@ __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_
 #pragma unroll
     for (int c = 0; c < PPL; ++c) y[c] = 0.0;
   }
-  T z[PPL];
-  row_probes<T, ZM>(a, own, r, q, o, z);
-  emit_moments<T, L>(a, own, o.node, y, z, q, mom);
+  if constexpr (ZM == 2) {
+    if (own) {
+      const double sd = sqrt(static_cast<double>(d));
+#pragma unroll
+      for (int c = 0; c < PPL; ++c) {
+        if (q * PPL + c >= a.k_batch) continue;
+        const double y0 = static_cast<double>(o.xo[c]) * sd;
+        mom[c * kBlock] += y[c] * y0;
+        mom[(PPL + c) * kBlock] += y[c] * y[c];
+      }
+    }
+  } else {
+    T z[PPL];
+    row_probes<T, ZM>(a, own, r, q, o, z);
+    emit_moments<T, L>(a, own, o.node, y, z, q, mom);
+  }
 }
 
 // Sum of X rows over the nonzeros e0+sub, e0+sub+P, ... < e1: U independent
@@ -377,17 +407,18 @@ __device__ inline void chunk_item(const StepArgs& a, int64_t c, int lane) {
 }
 
 // Block-level fixed-order reduction of the per-lane probe sums (LDS
-// s_mom[c][thread] for probe c of the thread's lane) into
-// partial[blockIdx.x][0..kp).
-template <typename T, int L>
+// s_mom[h * PPL + c][thread] for sum h of probe c of the thread's lane) into
+// partial[blockIdx.x][h][0..kp).
+template <typename T, int L, int NS>
 __device__ inline void block_partials(const StepArgs& a, const double (*s_mom)[kBlock]) {
   constexpr int PPL = 16 / sizeof(T);
   __syncthreads();
-  if (static_cast<int>(threadIdx.x) < a.kp) {
-    const int j = threadIdx.x, qq = j / PPL, cc = j % PPL;
+  const int cols = NS * a.kp;
+  if (static_cast<int>(threadIdx.x) < cols) {
+    const int h = threadIdx.x / a.kp, j = threadIdx.x % a.kp, qq = j / PPL, cc = j % PPL;
     double s = 0.0, comp = 0.0;
-    for (int t = qq; t < kBlock; t += L) neumaier(s, comp, s_mom[cc][t]);
-    a.partial[static_cast<int64_t>(blockIdx.x) * a.kp + j] = s + comp;
+    for (int t = qq; t < kBlock; t += L) neumaier(s, comp, s_mom[h * PPL + cc][t]);
+    a.partial[static_cast<int64_t>(blockIdx.x) * cols + threadIdx.x] = s + comp;
   }
 }
 
@@ -401,9 +432,10 @@ template <typename T, int L, int ZM>
 __global__ __launch_bounds__(kBlock) void k_split_finish(StepArgs a, int step_grid) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int P = kWave / L;
-  __shared__ double s_mom[PPL][kBlock];
+  constexpr int NS = kSums<ZM>;
+  __shared__ double s_mom[NS * PPL][kBlock];
 #pragma unroll
-  for (int c = 0; c < PPL; ++c) s_mom[c][threadIdx.x] = 0.0;
+  for (int c = 0; c < NS * PPL; ++c) s_mom[c][threadIdx.x] = 0.0;
   double* mom = &s_mom[0][threadIdx.x];
   const int lane = threadIdx.x & (kWave - 1), sub = lane / L, q = lane % L;
   const double* part = reinterpret_cast<const double*>(a.chunk_part);
@@ -425,17 +457,18 @@ __global__ __launch_bounds__(kBlock) void k_split_finish(StepArgs a, int step_gr
     finish_row<T, L, ZM, double>(a, sub == 0, r, a.row_ptr[r + 1] - a.row_ptr[r], tot, o, q, mom);
   }
   StepArgs b = a;
-  b.partial = a.partial + static_cast<int64_t>(step_grid) * a.kp;
-  block_partials<T, L>(b, s_mom);
+  b.partial = a.partial + static_cast<int64_t>(step_grid) * NS * a.kp;
+  block_partials<T, L, NS>(b, s_mom);
 }
 
 template <typename T, int L, int U, int ZM>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int PMAX = kWave / L;
-  __shared__ double s_mom[PPL][kBlock];
+  constexpr int NS = kSums<ZM>;
+  __shared__ double s_mom[NS * PPL][kBlock];
 #pragma unroll
-  for (int c = 0; c < PPL; ++c) s_mom[c][threadIdx.x] = 0.0;
+  for (int c = 0; c < NS * PPL; ++c) s_mom[c][threadIdx.x] = 0.0;
   double* mom = &s_mom[0][threadIdx.x];
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t W = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
@@ -464,17 +497,19 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
     }
     offset += a.bin_item_start[b + 1] - a.bin_item_start[b];
   }
-  block_partials<T, L>(a, s_mom);
+  block_partials<T, L, NS>(a, s_mom);
 }
 
 // Moment 0: Y_0 = Z.  Internal rows in order, 64/L rows per wavefront.
 template <typename T, int L, int ZM>
 __global__ __launch_bounds__(kBlock) void k_moment0(StepArgs a) {
+  static_assert(ZM != 2, "moment 0 needs the probes");
   constexpr int PPL = 16 / sizeof(T);
   constexpr int RPW = kWave / L;
-  __shared__ double s_mom[PPL][kBlock];
+  constexpr int NS = kSums<ZM>;
+  __shared__ double s_mom[NS * PPL][kBlock];
 #pragma unroll
-  for (int c = 0; c < PPL; ++c) s_mom[c][threadIdx.x] = 0.0;
+  for (int c = 0; c < NS * PPL; ++c) s_mom[c][threadIdx.x] = 0.0;
   double* mom = &s_mom[0][threadIdx.x];
   const int lane = threadIdx.x & (kWave - 1), q = lane % L, grp = lane / L;
   const int64_t n_waves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
@@ -497,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_moment0(StepArgs a) {
   for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < int64_t(a.split_blocks) * a.kp;
        t += static_cast<int64_t>(gridDim.x) * kBlock)
     sp[t] = 0.0;
-  block_partials<T, L>(a, s_mom);
+  block_partials<T, L, NS>(a, s_mom);
 }
 
 }  // namespace
@@ -585,27 +620,58 @@ __global__ __launch_bounds__(kBlock) void k_zcls(const int64_t* __restrict__ cla
     for (int64_t p = class_ptr[c]; p < class_ptr[c + 1]; ++p) zcls[inv[members[p]]] = static_cast<int32_t>(c);
 }
 
-// mu_pp[j0+j][m] = (1/N) sum over partial slots, for the `count` steps
-// m0 .. m0+count-1 stored in consecutive partial blocks of `slots` slots.
-// Thread t sums slots t/kp, t/kp + S, ... (S = 256/kp stripes) with
-// compensation; the stripes are then combined in order: a fixed order.
+// out[(j0 + j) * ld_out + (m0 + s) * NS + h] = (1/N) sum over the partial
+// slots of sum h of probe j, for the launches m0 + s stored in consecutive
+// partial blocks of step_stride doubles (slots x NS x kp each; one block per
+// launch).  Thread t sums slots t/cols, t/cols + S, ... (cols = NS kp, S =
+// 256/cols stripes) with compensation; the stripes are then combined in
+// order: a fixed order.
 __global__ __launch_bounds__(kBlock) void k_reduce_partials(const double* __restrict__ partial, int64_t slots,
-                                                            int kp, int k_batch, int m0, double inv_n,
-                                                            double* __restrict__ mu_pp, int M, int64_t j0) {
+                                                            int64_t step_stride, int NS, int kp, int k_batch,
+                                                            int m0, double inv_n, double* __restrict__ out,
+                                                            int64_t ld_out, int64_t j0) {
   __shared__ double red[kBlock];
   const int s = blockIdx.x;
-  const double* p = partial + static_cast<int64_t>(s) * slots * kp;
-  const int stripes = kBlock / kp;
-  const int j = threadIdx.x % kp, st = threadIdx.x / kp;
+  const int cols = NS * kp;
+  const double* p = partial + static_cast<int64_t>(s) * step_stride;
+  const int stripes = kBlock / cols;
+  const int c = threadIdx.x % cols, st = threadIdx.x / cols;
   double sum = 0.0, comp = 0.0;
   if (st < stripes)
-    for (int64_t b = st; b < slots; b += stripes) neumaier(sum, comp, p[b * kp + j]);
+    for (int64_t b = st; b < slots; b += stripes) neumaier(sum, comp, p[b * cols + c]);
   red[threadIdx.x] = sum + comp;
   __syncthreads();
-  if (static_cast<int>(threadIdx.x) < k_batch) {
-    double t = 0.0, c = 0.0;
-    for (int q = 0; q < stripes; ++q) neumaier(t, c, red[q * kp + threadIdx.x]);
-    mu_pp[(j0 + threadIdx.x) * M + m0 + s] = (t + c) * inv_n;
+  if (static_cast<int>(threadIdx.x) < cols && static_cast<int>(threadIdx.x) % kp < k_batch) {
+    double t = 0.0, cc = 0.0;
+    for (int q = 0; q < stripes; ++q) neumaier(t, cc, red[q * cols + threadIdx.x]);
+    const int h = threadIdx.x / kp, j = threadIdx.x % kp;
+    out[(j0 + j) * ld_out + static_cast<int64_t>(m0 + s) * NS + h] = (t + cc) * inv_n;
+  }
+}
+
+// Moments from the doubling steps, per probe: with r1[s] = Y_s.Y_{s-1} / N
+// and r2[s] = Y_s.Y_s / N (raw[j][2 s + 0/1], s >= 1),
+//   mu_1 = r1[1],  mu_{2s-1} = 2 r1[s] - mu_1,  mu_{2s} = 2 r2[s] - mu_0
+// (T_s T_{s-1} = (T_{2s-1} + T_1) / 2, T_s^2 = (T_{2s} + T_0) / 2); mu_0 is
+// already in mu_pp.
+__global__ __launch_bounds__(kBlock) void k_doubling_moments(const double* __restrict__ raw, int64_t ld_raw,
+                                                             int k_batch, int64_t j0, int M,
+                                                             double* __restrict__ mu_pp) {
+  const int64_t total = static_cast<int64_t>(k_batch) * M;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int64_t j = j0 + idx / M;
+    const int m = static_cast<int>(idx % M);
+    if (m == 0) continue;
+    const double* r = raw + j * ld_raw;
+    double v;
+    if (m & 1) {
+      const int sidx = (m + 1) / 2;
+      v = (m == 1) ? r[2] : 2.0 * r[2 * sidx] - r[2];
+    } else {
+      v = 2.0 * r[2 * (m / 2) + 1] - mu_pp[j * M];
+    }
+    mu_pp[j * M + m] = v;
   }
 }
 
@@ -743,12 +809,18 @@ struct MomentJob {
   const double* spikes = nullptr;  // device: removed eigenvalues, then their weights
   int n_spikes = 0;                // (added to mu as sum_s w_s T_m(lambda_s))
   bool timed = false;
+  bool doubling = false;  // global moments from products of Y_s (about M/2 launches)
 };
 
 template <typename T, int L, int ZM>
 nd_status launch_step_zm(const StepArgs& base, int grid, bool moment0, hipStream_t st) {
   if (moment0) {
-    hipLaunchKernelGGL((k_moment0<T, L, ZM>), dim3(grid), dim3(kBlock), 0, st, base);
+    if constexpr (ZM == 2) {
+      set_error("internal: moment 0 launched as a doubling step");
+      return ND_EUNSUPPORTED;
+    } else {
+      hipLaunchKernelGGL((k_moment0<T, L, ZM>), dim3(grid), dim3(kBlock), 0, st, base);
+    }
   } else {
     hipLaunchKernelGGL((k_cheb_step<T, L, 8, ZM>), dim3(grid), dim3(kBlock), 0, st, base);
     if (base.n_split > 0) {
@@ -762,7 +834,11 @@ nd_status launch_step_zm(const StepArgs& base, int grid, bool moment0, hipStream
 
 template <typename T, int L>
 nd_status launch_step_kernels(const StepArgs& base, int grid, bool moment0, hipStream_t st) {
-  return base.zmode ? launch_step_zm<T, L, 1>(base, grid, moment0, st) : launch_step_zm<T, L, 0>(base, grid, moment0, st);
+  switch (base.zmode) {
+    case 0: return launch_step_zm<T, L, 0>(base, grid, moment0, st);
+    case 1: return launch_step_zm<T, L, 1>(base, grid, moment0, st);
+    default: return launch_step_zm<T, L, 2>(base, grid, moment0, st);
+  }
 }
 
 template <typename T>
@@ -799,10 +875,15 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
       for (hipEvent_t x : e) (void)hipEventDestroy(x);
     }
   } ev_free{evs};
-  if (!mu_pp) {
-    ND_CHECK(g->ws_misc.ensure(static_cast<size_t>(job.k) * M * sizeof(double)));
-    mu_pp = g->ws_misc.as<double>();
-  }
+  // doubling: launches s = 1..S give moments 2s-1 and 2s (S = floor(M/2));
+  // otherwise launch m gives moment m
+  const int last = job.doubling ? M / 2 : M - 1;
+  const int64_t ld_raw = 2 * (static_cast<int64_t>(last) + 1);
+  const size_t n_pp = job.mu_pp ? 0 : static_cast<size_t>(job.k) * M;
+  const size_t n_raw = job.doubling ? static_cast<size_t>(job.k) * ld_raw : 0;
+  if (n_pp + n_raw) ND_CHECK(g->ws_misc.ensure((n_pp + n_raw) * sizeof(double)));
+  if (!mu_pp) mu_pp = g->ws_misc.as<double>();
+  double* raw = job.doubling ? g->ws_misc.as<double>() + n_pp : nullptr;
   const int bmax = max_block_probes();
   for (int j0 = 0; j0 < job.k; j0 += bmax) {
     const int kb = job.k - j0 < bmax ? job.k - j0 : bmax;
@@ -820,10 +901,11 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     const int grid = grid_for(sc->n_items > 0 ? sc->n_items : 1, kWavesPerBlock, step_grid<T>(L));
     const int split_blocks = sc->n_split > 0 ? grid_for(sc->n_split, kWavesPerBlock, grid) : 0;
     const int64_t slots = static_cast<int64_t>(grid) + split_blocks;
-    const int64_t per_step = slots * kp;
+    const int NSd = job.doubling ? 2 : 1;          // sums per probe of the step launches
+    const int64_t per_step = slots * kp * NSd;
     int R = static_cast<int>((int64_t(64) << 20) / (per_step * 8));
     if (R < 1) R = 1;
-    if (R > M) R = M;
+    if (R > last + 1) R = last + 1;
     ND_CHECK(g->ws_partial.ensure(static_cast<size_t>(R) * per_step * sizeof(double)));
     double* partial = g->ws_partial.as<double>();
 
@@ -887,15 +969,28 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     a.ld = M;
     a.accumulate = j0 > 0 ? 1 : 0;
     a.cv_g = job.cv_g;
-    for (int m = 0; m < M; ++m) {
+    const double inv_n = 1.0 / static_cast<double>(N);
+    for (int m = 0; m <= last; ++m) {
       a.m = m;
-      a.partial = partial + static_cast<int64_t>(m % R) * per_step;
+      // ring position of this launch's partials; with doubling, moment 0 is
+      // reduced on its own right away (one sum per probe) and the ring
+      // starts at launch 1
+      const int pos = job.doubling ? (m == 0 ? 0 : (m - 1) % R) : m % R;
+      a.partial = partial + static_cast<int64_t>(pos) * per_step;
       if (m == 0) {
         a.first = 1;  // no X_{m-1} operand at moment 0
         a.xg = nullptr;
         a.xio = nullptr;
+        a.zmode = zmode;
         ND_CHECK(launch_step<T>(L, a, grid, true, st));
+        if (job.doubling) {
+          hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, partial, slots, per_step, 1, kp, kb, 0,
+                             inv_n, mu_pp, static_cast<int64_t>(M), static_cast<int64_t>(j0));
+          ND_LAUNCH_CHECK();
+          continue;
+        }
       } else {
+        if (job.doubling) a.zmode = 2;
         a.first = (m == 1) ? 1 : 0;
         a.xg = (m & 1) ? A : B;
         a.xio = (m & 1) ? B : A;
@@ -910,12 +1005,21 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
         ND_CHECK(launch_step<T>(L, a, grid, false, st));
         if (job.timed) ND_HIP(hipEventRecord(e1, st));
       }
-      if ((m + 1) % R == 0 || m == M - 1) {
-        const int m0 = m - (m % R);
-        hipLaunchKernelGGL(k_reduce_partials, dim3(m - m0 + 1), dim3(kBlock), 0, st, partial, slots, kp, kb, m0,
-                           1.0 / static_cast<double>(N), mu_pp, M, static_cast<int64_t>(j0));
+      if (pos + 1 == R || m == last) {
+        const int m0 = m - pos;
+        if (job.doubling)
+          hipLaunchKernelGGL(k_reduce_partials, dim3(pos + 1), dim3(kBlock), 0, st, partial, slots, per_step, 2, kp,
+                             kb, m0, inv_n, raw, ld_raw, static_cast<int64_t>(j0));
+        else
+          hipLaunchKernelGGL(k_reduce_partials, dim3(pos + 1), dim3(kBlock), 0, st, partial, slots, per_step, 1, kp,
+                             kb, m0, inv_n, mu_pp, static_cast<int64_t>(M), static_cast<int64_t>(j0));
         ND_LAUNCH_CHECK();
       }
+    }
+    if (job.doubling) {
+      hipLaunchKernelGGL(k_doubling_moments, dim3(grid_for(static_cast<int64_t>(kb) * M, kBlock)), dim3(kBlock), 0,
+                         st, raw, ld_raw, kb, static_cast<int64_t>(j0), M, mu_pp);
+      ND_LAUNCH_CHECK();
     }
   }
   if (job.timed) {
@@ -947,8 +1051,8 @@ nd_status check_common(const nd_graph* g, const nd_motifs* motifs, int32_t n_pro
   ND_REQUIRE(g->n > 0, "%s: the graph has no edges (no node survives)", who);
   ND_REQUIRE(n_probes >= 1, "%s: n_probes=%d must be >= 1", who, n_probes);
   ND_REQUIRE(n_moments >= 1, "%s: n_moments=%d must be >= 1", who, n_moments);
-  ND_REQUIRE((flags & ~(ND_PROBE_GAUSSIAN | ND_STATE_FP64 | ND_TIME_STEPS)) == 0, "%s: unknown flags 0x%x", who,
-             flags);
+  ND_REQUIRE((flags & ~(ND_PROBE_GAUSSIAN | ND_STATE_FP64 | ND_TIME_STEPS | ND_MOMENT_DOUBLING)) == 0,
+             "%s: unknown flags 0x%x", who, flags);
   ND_REQUIRE(motifs == nullptr || motifs->n == g->n, "%s: motifs belong to another graph", who);
   int dev = -1;
   ND_HIP(hipGetDevice(&dev));
@@ -1011,6 +1115,7 @@ nd_status nd_cheb_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
   job.mu = mu;
   job.mu_pp = mu_pp;
   job.timed = (flags & ND_TIME_STEPS) != 0;
+  job.doubling = (flags & ND_MOMENT_DOUBLING) != 0;
   nd_graph* gm = const_cast<nd_graph*>(g);
   if (flags & ND_STATE_FP64) return nd::run_moments<double>(gm, job, nd::as_stream(stream));
   return nd::run_moments<float>(gm, job, nd::as_stream(stream));
@@ -1022,6 +1127,9 @@ nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
   nd::clear_error();
   ND_CHECK(nd::check_common(g, motifs, n_probes, n_moments, flags, "nd_ldos_moments"));
   ND_REQUIRE(ldos != nullptr, "nd_ldos_moments: ldos is NULL");
+  ND_REQUIRE((flags & ND_MOMENT_DOUBLING) == 0,
+             "nd_ldos_moments: ND_MOMENT_DOUBLING applies to global moments only (the per-node estimate "
+             "needs every T_m(H) z)");
   nd::MomentJob job;
   job.motifs = motifs;
   job.k = n_probes;

@@ -196,6 +196,53 @@ def test_global_moments(case, nd, k, M):
     assert np.max(np.abs(mupp - mupp_o)) < TOL_MU
 
 
+@pytest.mark.parametrize("k,M", [(20, 100), (64, 61), (3, 200), (100, 30), (5, 1), (5, 2), (5, 3)])
+def test_global_moments_doubling(case, nd, k, M):
+    """ND_MOMENT_DOUBLING: the same estimates from floor(M/2) products."""
+    import torch
+    name, _, g_or, g = case
+    H = og.normalized_adjacency(g_or)
+    Z = orng.rademacher(g_or.n, k, 5)
+    mu_o, mupp_o, _ = kpm.stochastic_moments(H, Z, M, ldos=False)
+    mu = _zeros(M, torch.float64)
+    mupp = _zeros(k * M, torch.float64)
+    nd.nd_cheb_moments(g, None, k, M, 5, nd.ND_MOMENT_DOUBLING | nd.ND_TIME_STEPS, mu, mupp)
+    assert nd.nd_graph_step_timing(g)[1] == (M // 2) * ((k + 63) // 64)
+    mu, mupp = mu.cpu().numpy(), mupp.cpu().numpy().reshape(k, M)
+    assert np.all(mupp[:, 0] == 1.0)
+    assert np.max(np.abs(mu - mu_o)) < TOL_MU
+    assert np.max(np.abs(mupp - mupp_o)) < TOL_MU
+
+
+def test_doubling_fp64_filtered_gaussian(case, nd):
+    import torch
+    name, _, g_or, g = case
+    k, M = 12, 75
+    H = og.normalized_adjacency(g_or)
+    mu = _zeros(M, torch.float64)
+    # fp64 state against the oracle
+    Z = orng.rademacher(g_or.n, k, 8)
+    mu_o, _, _ = kpm.stochastic_moments(H, Z, M, ldos=False)
+    nd.nd_cheb_moments(g, None, k, M, 8, nd.ND_STATE_FP64 | nd.ND_MOMENT_DOUBLING, mu)
+    assert np.max(np.abs(mu.cpu().numpy() - mu_o)) < TOL_FP64
+    # twin filtering: smooth moments of the projected probes
+    m = nd.nd_motif_filter(g, 3, 0x3)
+    cls = twins.twin_classes(g_or, "both")
+    lam = [twins.class_eigenvalue(g_or, c) for c in cls]
+    _, mu_s, _, _ = twins.filtered_moments(H, Z, M, cls, ldos=False, lambdas=lam)
+    nd.nd_cheb_moments(g, m, k, M, 8, nd.ND_MOMENT_DOUBLING, mu)
+    assert np.max(np.abs(mu.cpu().numpy() - mu_s)) < TOL_MU
+    # Gaussian probes (the GPU's own fp32 probe values feed the oracle)
+    Zd = _zeros(g.n * k, torch.float32)
+    nd.nd_make_probes(g, None, k, 9, nd.ND_PROBE_GAUSSIAN, Zd)
+    Zg = Zd.cpu().numpy().reshape(g.n, k).astype(np.float64)
+    mu_g, _, _ = kpm.stochastic_moments(H, Zg, M, ldos=False)
+    nd.nd_cheb_moments(g, None, k, M, 9, nd.ND_PROBE_GAUSSIAN | nd.ND_MOMENT_DOUBLING, mu)
+    assert np.max(np.abs(mu.cpu().numpy() - mu_g)) < TOL_MU * 10
+    with pytest.raises(nd.NDError):
+        nd.nd_ldos_moments(g, None, k, M, 8, nd.ND_MOMENT_DOUBLING, _zeros(g.n * M, torch.float64))
+
+
 def test_global_moments_fp64_state(case, nd):
     import torch
     name, _, g_or, g = case

@@ -159,3 +159,24 @@ def test_hutchinson_error_decays():
         errs.append(np.abs(mu - mu_x)[1:].max())
     assert errs[1] < errs[0]
     assert errs[1] < 5.0 * np.sqrt(2.0 / g.n / 64)
+
+
+def test_doubling_identities():
+    """T_s T_{s-1} = (T_{2s-1} + T_1)/2 and T_s^2 = (T_{2s} + T_0)/2 (product
+    formula of Chebyshev polynomials, used by the KPM review the paper cites
+    to halve the products for traces): per probe, the direct moments equal
+    the ones formed from inner products of the vectors y_s = T_s(H) z."""
+    n, s, d = sg.rmat(8, 6, seed=3)
+    g = og.build_csr(n, s, d)
+    H = og.normalized_adjacency(g)
+    Z = orng.rademacher(g.n, 3, 2)
+    M = 41
+    _, mupp, _ = kpm.stochastic_moments(H, Z, M, ldos=False)
+    Y = list(kpm.cheb_vectors(H, Z, M // 2 + 1))
+    dot = lambda a, b: (a * b).sum(axis=0) / g.n   # noqa: E731
+    for sidx in range(1, M // 2 + 1):
+        even = 2.0 * dot(Y[sidx], Y[sidx]) - dot(Y[0], Y[0])
+        odd = 2.0 * dot(Y[sidx], Y[sidx - 1]) - dot(Y[1], Y[0])
+        if 2 * sidx < M:
+            assert np.allclose(even, mupp[:, 2 * sidx], atol=1e-12)
+        assert np.allclose(odd, mupp[:, 2 * sidx - 1], atol=1e-12)
