@@ -1,5 +1,5 @@
-"""Twin motifs and probe projection (Sec. 3.4, motif filtering; Sec. 3.3
-for the spectral signature of the motifs).
+"""Twin motifs and probe projection (Sec. 3.4, motif filtering, and the
+motif figure there that lists the spectral signature of each motif).
 
 Oracle: test infrastructure only (tests, the smoke check and the CPU baseline
 of the benchmark use it; the GPU library never does).
