@@ -15,6 +15,7 @@ KDD 2019 (arXiv:1905.09758):
 * :mod:`oracle.rng`          -- probe vectors (Sec. 3.1, probe estimators)
 * :mod:`oracle.kpm`          -- Chebyshev moments, exact and stochastic (Sec. 3.1)
 * :mod:`oracle.twins`        -- twin motifs and probe projection (Sec. 3.4)
+* :mod:`oracle.gql`          -- Gauss quadrature and Lanczos, GQL (Sec. 3.2)
 * :mod:`oracle.reconstruct`  -- Jackson damping, density, histogram (Sec. 2.2, 3.1, 4.1)
 * :mod:`oracle.cv`           -- learned control variate: features, MLP, estimator
                                 (not in the paper; parity unpinned by the paper)

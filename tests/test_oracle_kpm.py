@@ -180,3 +180,57 @@ def test_doubling_identities():
         if 2 * sidx < M:
             assert np.allclose(even, mupp[:, 2 * sidx], atol=1e-12)
         assert np.allclose(odd, mupp[:, 2 * sidx - 1], atol=1e-12)
+
+
+# ------------------------------------------------------------ GQL (Sec. 3.2)
+from oracle import gql  # noqa: E402
+
+
+def test_gql_moments_equal_kpm_up_to_degree_2k_minus_1():
+    """The K-node Gauss rule integrates polynomials of degree <= 2K-1 exactly,
+    so its Chebyshev moments are the KPM estimates of the same probes."""
+    n, s, d = sg.rmat(9, 6, seed=2)
+    g = og.build_csr(n, s, d)
+    H = og.normalized_adjacency(g)
+    Z = orng.rademacher(g.n, 4, 5)
+    for K in (5, 12, 30):
+        rules = gql.gql_probes(H, Z, K)
+        mu_g = gql.gql_moments(rules, 2 * K)
+        mu_k, _, _ = kpm.stochastic_moments(H, Z, 2 * K, ldos=False)
+        assert np.allclose(mu_g, mu_k, atol=1e-9)
+        # degree 2K is not integrated exactly in general
+    rules = gql.gql_probes(H, Z, 5)
+    mu_g = gql.gql_moments(rules, 12)
+    mu_k, _, _ = kpm.stochastic_moments(H, Z, 12, ldos=False)
+    assert np.abs(mu_g[10:] - mu_k[10:]).max() > 1e-6
+
+
+def test_gql_with_unit_probes_gives_the_pdos():
+    """z = e_k (Sec. 3.2): the rule estimates the PDOS of node k, and its
+    Chebyshev moments are the exact PDOS moments d_mk for m <= 2K - 1."""
+    n, s, d = sg.erdos_renyi(60, 0.1, seed=4)
+    g = og.build_csr(n, s, d)
+    H = og.normalized_adjacency(g)
+    _, l_x = kpm.exact_moments_eig(H, 16)
+    K = 8
+    for k in (0, 7, g.n - 1):
+        e = np.zeros((g.n, 1))
+        e[k, 0] = 1.0
+        rules = gql.gql_probes(H, e, K)
+        tau, w = rules[0]
+        assert abs(w.sum() * g.n - 1.0) < 1e-12          # weights carry |z|^2 / N
+        mu = gql.gql_moments(rules, 2 * K) * g.n
+        assert np.allclose(mu, l_x[k, :2 * K], atol=1e-10)
+
+
+def test_gql_breakdown_and_histogram():
+    # the 4-cycle has 3 distinct eigenvalues: Lanczos from a generic probe stops after 3 steps
+    g = og.build_csr(*sg.cycle(4))
+    H = og.normalized_adjacency(g)
+    a, b = gql.lanczos(H, np.array([1.0, 1.0, -1.0, 1.0]), 10)
+    assert a.size <= 3
+    tau, w = gql.quadrature(a, b)
+    assert set(np.round(tau, 12)) <= {-1.0, 0.0, 1.0}
+    rules = gql.gql_probes(H, orng.rademacher(4, 3, 1), 10)
+    h = gql.gql_histogram(rules, 4)
+    assert abs(h.sum() - 1.0) < 1e-12
