@@ -12,6 +12,7 @@
  *   - stochastic trace / diagonal estimation with a block of probes:
  *     Sec. 3.1 (eq. probe_trace, eq. probe_diag);
  *   - motif (twin) detection by hashing and probe projection: Sec. 3.4;
+ *   - Gauss quadrature and Lanczos (GQL) for the DOS: Sec. 3.2;
  *   - Jackson-damped reconstruction and spectral histograms: Sec. 2.2
  *     (eqn reg_dos and the histogram that follows it), Sec. 3.1 (eqn orth),
  *     Sec. 4.1 (Jackson's theorem).
@@ -217,6 +218,47 @@ nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
                           int32_t n_moments, uint64_t probe_seed, uint32_t flags,
                           const float* cv_g, double* ldos, double* ldos_sq, double* mu,
                           void* stream);
+
+/* --------------------------------------------------------------- GQL */
+
+/* Gauss quadrature and Lanczos (Sec. 3.2).  For every probe z_j (the same
+ * probes as nd_cheb_moments: seed, flags, projection with `motifs`), K =
+ * n_steps Lanczos steps on H from v_1 = z_j/|z_j| (three-term recurrence, no
+ * reorthogonalization) give the tridiagonal Gamma (diagonal alpha, off-
+ * diagonal beta); its eigenvalues tau_i and squared first eigenvector
+ * components p_1i^2 form the K-node Gauss rule of the measure
+ * sum_i (q_i^T z_j)^2 delta(lambda - lambda_i), so that
+ *   (1/k) sum_j sum_i weights[j][i] delta(lambda - nodes[j][i])
+ * estimates the DOS (Chebyshev moments equal to the KPM estimates of the
+ * same probes up to degree 2K-1).
+ *   n_steps  1..4096
+ *   flags    ND_PROBE_RADEMACHER | ND_PROBE_GAUSSIAN, optionally ND_STATE_FP64
+ *            (fp64 Lanczos vectors), ND_TIME_STEPS
+ *   nodes    device double [n_probes][n_steps]: tau (unordered within a probe)
+ *   weights  device double [n_probes][n_steps]: p_1i^2 |z_j|^2 / N
+ *   steps    device int32 [n_probes] or NULL: steps taken; a probe stops
+ *            early when beta falls below 1e-10 (1e-5 with fp32 vectors): an
+ *            invariant subspace, where the rule is exact; entries past it
+ *            are 0
+ *   alpha, beta  device double [n_probes][n_steps] or NULL: the Lanczos
+ *            coefficients (beta[j][i] couples steps i and i+1)
+ * With motifs, the rule describes the smooth part; the spikes of
+ * nd_motif_info carry the removed mass.  Synchronises `stream`.
+ * Errors: ND_EINVAL (arguments), ND_EDEVICE (device failure or a tridiagonal
+ * eigenproblem that did not converge), ND_ENOMEM. */
+nd_status nd_gql(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes, int32_t n_steps,
+                 uint64_t probe_seed, uint32_t flags, double* nodes, double* weights, int32_t* steps,
+                 double* alpha, double* beta, void* stream);
+
+/* From the rules of nd_gql (device arrays [n_probes][n_steps]): Chebyshev
+ * moments mu[m] = (1/k) sum_j sum_i w_ji T_m(tau_ji), m < n_moments (device
+ * double, or NULL), and/or the histogram of the point masses over n_bins
+ * equal bins of [lo, hi] (half-open except the last; device double
+ * [n_bins], or NULL).  Nodes are clamped to [-1, 1], the interval holding
+ * the spectrum of H, first.  Asynchronous on `stream`. */
+nd_status nd_gql_density(const double* nodes, const double* weights, int32_t n_probes, int32_t n_steps,
+                         int32_t n_moments, double* mu, int32_t n_bins, double lo, double hi, double* hist,
+                         void* stream);
 
 /* --------------------------------------------------------------- reconstruction */
 

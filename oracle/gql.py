@@ -73,13 +73,15 @@ def gql_moments(rules, M: int) -> np.ndarray:
 
 def gql_histogram(rules, n_bins: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
     """The averaged point masses binned like the other histograms (half-open
-    bins, last closed)."""
+    bins, last closed).  Nodes are clamped to [-1, 1], the interval holding
+    the spectrum of H: a rule computed in finite precision can place the node
+    of the eigenvalue 1 (or -1) a rounding error outside it."""
     from .reconstruct import bin_edges, spike_bin
     e = bin_edges(n_bins, lo, hi)
     h = np.zeros(n_bins)
     for tau, w in rules:
         for t, x in zip(tau, w):
-            b = spike_bin(float(t), e)
+            b = spike_bin(min(max(float(t), -1.0), 1.0), e)
             if b is not None:
                 h[b] += x
     return h / len(rules)

@@ -37,7 +37,7 @@ EXPORTS = (
     "nd_graph_free",
     "nd_motif_filter", "nd_motif_info", "nd_motif_export", "nd_motif_export_lambda", "nd_motifs_free",
     "nd_make_probes",
-    "nd_cheb_moments", "nd_ldos_moments", "nd_reconstruct", "nd_node_features", "nd_column_stats",
+    "nd_cheb_moments", "nd_ldos_moments", "nd_gql", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_column_stats",
     "nd_mlp_forward", "nd_mlp_grad", "nd_adam_step", "nd_last_error",
 )
 
@@ -82,6 +82,8 @@ _sig("nd_motifs_free", [_vp], None)
 _sig("nd_make_probes", [_vp, _vp, _i32, _u64, _u32, _vp, _vp])
 _sig("nd_cheb_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp])
 _sig("nd_ldos_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp, _vp])
+_sig("nd_gql", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp, _vp, _vp])
+_sig("nd_gql_density", [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _dbl, _dbl, _vp, _vp])
 _sig("nd_reconstruct", [_vp, _i64, _i32, _u32, _vp, _vp, _i32, _i32, _dbl, _dbl, _vp, _i32, _vp, _vp])
 _sig("nd_last_error", [], ctypes.c_char_p)
 _HAS_CV = hasattr(_lib, "nd_node_features")
@@ -280,6 +282,31 @@ def nd_ldos_moments(g: Graph, motifs, n_probes: int, n_moments: int, seed: int, 
     pm = _dev(mu, torch.float64, n_moments, "mu")
     _check(_lib.nd_ldos_moments(g.handle, _h(motifs), n_probes, n_moments, seed, flags, pg, pl, ps, pm,
                                 _stream(stream)), "nd_ldos_moments")
+
+
+def nd_gql(g: Graph, motifs, n_probes: int, n_steps: int, seed: int, flags: int, nodes, weights, steps=None,
+           alpha=None, beta=None, stream=None):
+    import torch
+    kk = n_probes * n_steps
+    pn = _dev(nodes, torch.float64, kk, "nodes")
+    pw = _dev(weights, torch.float64, kk, "weights")
+    ps = _dev(steps, torch.int32, n_probes, "steps")
+    pa = _dev(alpha, torch.float64, kk, "alpha")
+    pb = _dev(beta, torch.float64, kk, "beta")
+    _check(_lib.nd_gql(g.handle, _h(motifs), n_probes, n_steps, seed, flags, pn, pw, ps, pa, pb, _stream(stream)),
+           "nd_gql")
+
+
+def nd_gql_density(nodes, weights, n_probes: int, n_steps: int, n_moments: int = 0, mu=None, n_bins: int = 0,
+                   lo: float = -1.0, hi: float = 1.0, hist=None, stream=None):
+    import torch
+    kk = n_probes * n_steps
+    pn = _dev(nodes, torch.float64, kk, "nodes")
+    pw = _dev(weights, torch.float64, kk, "weights")
+    pm = _dev(mu, torch.float64, n_moments, "mu") if mu is not None else None
+    ph = _dev(hist, torch.float64, n_bins, "hist") if hist is not None else None
+    _check(_lib.nd_gql_density(pn, pw, n_probes, n_steps, n_moments, pm, n_bins, lo, hi, ph, _stream(stream)),
+           "nd_gql_density")
 
 
 def nd_reconstruct(mu, n_rows: int, n_moments: int, kernel: int = ND_KERNEL_JACKSON, spikes=(),

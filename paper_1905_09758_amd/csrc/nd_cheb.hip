@@ -122,7 +122,8 @@ struct StepArgs {
   int64_t n_split;         // split rows are internal rows [0, n_split)
   int slot_nnz;            // nonzeros per slot and gather batch (4 or 8)
   int zmode;               // 0: probe rows read from z; 1: Rademacher rows regenerated;
-                           // 2: doubling steps (products of Y_m with Y_m and Y_{m-1}, no probes)
+                           // 2: doubling steps (products of Y_m with Y_m and Y_{m-1}, no probes);
+                           // 3: Lanczos steps (per-probe scales, product with the current vector)
   uint64_t seed;           // probe seed and index of this block's first probe (zmode 1)
   int64_t j0;
   const int32_t* zcls;     // zmode 1 with twin filtering: class of each internal row or -1
@@ -143,12 +144,17 @@ struct StepArgs {
   int64_t ld;       // leading dimension of ldos / cv_g (= number of moments)
   int accumulate;   // add to ldos instead of overwriting (later probe blocks)
   const float* cv_g;
+  const double* lz;  // Lanczos steps: [2][kp] scales of the stored current and previous vectors
 };
 
 // Per-probe sums a row epilogue produces: z.Y_m (probe modes), or the two
 // products Y_m.Y_{m-1} and Y_m.Y_m of the doubling steps.
 template <int ZM>
 constexpr int kSums = ZM == 2 ? 2 : 1;
+
+// Modes whose rows need their own entry of the gathered block.
+template <int ZM>
+constexpr bool kOwnRow = ZM == 2 || ZM == 3;
 
 // Per-row epilogue: given Y_m(i, probes of this lane) in fp64 and the probe
 // values z, form the estimator terms v_ij = z_ij y_ij (+ g_im (1 - z_ij^2)
@@ -199,7 +205,7 @@ template <typename T, int ZM>
 struct RowOperands {
   T xp[16 / sizeof(T)];
   T z[ZM == 0 ? 16 / sizeof(T) : 1];
-  T xo[ZM == 2 ? 16 / sizeof(T) : 1];
+  T xo[kOwnRow<ZM> ? 16 / sizeof(T) : 1];
   int64_t node;
 };
 
@@ -213,17 +219,17 @@ __device__ inline void load_row_operands(const StepArgs& a, bool own, int64_t r,
 #pragma unroll
     for (int c = 0; c < PPL; ++c) o.z[c] = T(0);
   }
-  if constexpr (ZM == 2) {
+  if constexpr (kOwnRow<ZM>) {
 #pragma unroll
     for (int c = 0; c < PPL; ++c) o.xo[c] = T(0);
   }
   if (own) {
     if (!a.first) load16_nt<T>(reinterpret_cast<const T*>(a.xio) + r * a.kp + q * PPL, o.xp);
-    if constexpr (ZM != 2) {
+    if constexpr (!kOwnRow<ZM>) {
       if (ZM == 1 || a.ldos || a.cv_g) o.node = a.perm[r];
     }
     if constexpr (ZM == 0) load16_nt<T>(reinterpret_cast<const T*>(a.z) + r * a.kp + q * PPL, o.z);
-    if constexpr (ZM == 2) load16<T>(reinterpret_cast<const T*>(a.xg) + r * a.kp + q * PPL, o.xo);
+    if constexpr (kOwnRow<ZM>) load16<T>(reinterpret_cast<const T*>(a.xg) + r * a.kp + q * PPL, o.xo);
   }
 }
 
@@ -259,10 +265,36 @@ __device__ inline void row_probes(const StepArgs& a, bool own, int64_t r, int q,
 // epilogue on Y = sqrt(d) X.  Doubling steps add Y_{m+1}.Y_m and
 // Y_{m+1}.Y_{m+1} per probe instead (T_{m+1} T_m = (T_{2m+1} + T_1)/2 and
 // T_{m+1}^2 = (T_{2m+2} + T_0)/2 turn them into two moments each).
+// Lanczos steps (ZM == 3) store W = c1 D^{-1} A X - c2 X_prev with per-probe
+// scales c1, c2 of the stored vectors, and add d c1 X(r) W(r) per probe (the
+// numerator of alpha = <v, H v>).
 template <typename T, int L, int ZM, typename A>
 __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_t d, const A (&acc)[16 / sizeof(T)],
                                   const RowOperands<T, ZM>& o, int q, double* mom) {
   constexpr int PPL = 16 / sizeof(T);
+  if constexpr (ZM == 3) {
+    if (own) {
+      T* xo = reinterpret_cast<T*>(a.xio) + r * a.kp + q * PPL;
+      T xn[PPL];
+      const A invd = A(1) / static_cast<A>(d);
+#pragma unroll
+      for (int c = 0; c < PPL; ++c) {
+        const int j = q * PPL + c;
+        const A c1 = static_cast<A>(a.lz[j]), c2 = static_cast<A>(a.lz[a.kp + j]);
+        xn[c] = a.first ? static_cast<T>(acc[c] * invd * c1)
+                        : static_cast<T>(acc[c] * invd * c1 - c2 * static_cast<A>(o.xp[c]));
+      }
+      store16_nt<T>(xo, xn);
+      const double dd = static_cast<double>(d);
+#pragma unroll
+      for (int c = 0; c < PPL; ++c) {
+        const int j = q * PPL + c;
+        if (j >= a.k_batch) continue;
+        mom[c * kBlock] += dd * (a.lz[j] * static_cast<double>(o.xo[c])) * static_cast<double>(xn[c]);
+      }
+    }
+    return;
+  }
   double y[PPL];
   if (own) {
     T* xo = reinterpret_cast<T*>(a.xio) + r * a.kp + q * PPL;
@@ -503,7 +535,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
 // Moment 0: Y_0 = Z.  Internal rows in order, 64/L rows per wavefront.
 template <typename T, int L, int ZM>
 __global__ __launch_bounds__(kBlock) void k_moment0(StepArgs a) {
-  static_assert(ZM != 2, "moment 0 needs the probes");
+  static_assert(!kOwnRow<ZM>, "moment 0 needs the probes");
   constexpr int PPL = 16 / sizeof(T);
   constexpr int RPW = kWave / L;
   constexpr int NS = kSums<ZM>;
@@ -815,8 +847,8 @@ struct MomentJob {
 template <typename T, int L, int ZM>
 nd_status launch_step_zm(const StepArgs& base, int grid, bool moment0, hipStream_t st) {
   if (moment0) {
-    if constexpr (ZM == 2) {
-      set_error("internal: moment 0 launched as a doubling step");
+    if constexpr (kOwnRow<ZM>) {
+      set_error("internal: moment 0 launched as a doubling or Lanczos step");
       return ND_EUNSUPPORTED;
     } else {
       hipLaunchKernelGGL((k_moment0<T, L, ZM>), dim3(grid), dim3(kBlock), 0, st, base);
@@ -837,7 +869,8 @@ nd_status launch_step_kernels(const StepArgs& base, int grid, bool moment0, hipS
   switch (base.zmode) {
     case 0: return launch_step_zm<T, L, 0>(base, grid, moment0, st);
     case 1: return launch_step_zm<T, L, 1>(base, grid, moment0, st);
-    default: return launch_step_zm<T, L, 2>(base, grid, moment0, st);
+    case 2: return launch_step_zm<T, L, 2>(base, grid, moment0, st);
+    default: return launch_step_zm<T, L, 3>(base, grid, moment0, st);
   }
 }
 
@@ -856,6 +889,110 @@ nd_status launch_step(int L, const StepArgs& a, int grid, bool moment0, hipStrea
   }
   set_error("internal: unsupported lane count %d", L);
   return ND_EUNSUPPORTED;
+}
+
+// Per-probe-block state shared by the moment and Lanczos drivers: schedule,
+// recurrence buffers (Z, A = X_0, B), the probe block (projected when
+// filtering) and the step arguments.
+template <typename T>
+struct BlockSetup {
+  int kp = 0, L = 0, grid = 0, split_blocks = 0, zmode = 0;
+  int64_t slots = 0;
+  T *Z = nullptr, *A = nullptr, *B = nullptr;
+  StepArgs a{};
+};
+
+template <typename T>
+nd_status setup_block(nd_graph* g, const MomentJob& job, int j0, int kb, hipStream_t st, BlockSetup<T>& bs) {
+  constexpr int PPL = 16 / sizeof(T);
+  const int64_t N = g->n;
+  const int M = job.M;
+  const int kp = pow2_at_least(kb < PPL ? PPL : kb);
+  const int L = kp * static_cast<int>(sizeof(T)) / 16;
+  Schedule* sc = nullptr;
+  ND_CHECK(get_schedule(g, L, st, &sc));
+  Internal* in = g->internal.get();
+  const size_t blk = static_cast<size_t>(N) * kp * sizeof(T);
+  ND_CHECK(g->ws_state.ensure(3 * blk));
+  ND_CHECK(g->ws_chunk.ensure(static_cast<size_t>(sc->n_chunks > 0 ? sc->n_chunks : 1) * kp * sizeof(double)));
+  T* Z = g->ws_state.as<T>();
+  T* A = Z + static_cast<int64_t>(N) * kp;
+  T* B = A + static_cast<int64_t>(N) * kp;
+  const int grid = grid_for(sc->n_items > 0 ? sc->n_items : 1, kWavesPerBlock, step_grid<T>(L));
+  const int split_blocks = sc->n_split > 0 ? grid_for(sc->n_split, kWavesPerBlock, grid) : 0;
+  const int64_t slots = static_cast<int64_t>(grid) + split_blocks;
+
+  hipLaunchKernelGGL(k_probes<T>, dim3(grid_for(N * kp, kBlock)), dim3(kBlock), 0, st, N, kp, kb,
+                     static_cast<int64_t>(j0), job.seed, job.gaussian ? 1 : 0, in->row_ptr, in->perm, Z, A);
+  ND_LAUNCH_CHECK();
+  // Rademacher rows are regenerated inside the step kernels (no probe-block
+  // reads); the projected rows of twin classes come from a small table
+  const int zmode = (!job.gaussian && !probe_buffer_forced()) ? 1 : 0;
+  const bool filt = job.motifs && job.motifs->n_classes > 0;
+  int32_t* zcls = nullptr;
+  T* zcls_val = nullptr;
+  if (filt) {
+    if (zmode) {
+      const size_t nc = static_cast<size_t>(job.motifs->n_classes);
+      ND_CHECK(g->ws_zcls.ensure(static_cast<size_t>(N) * 4 + 256 + nc * kp * sizeof(T)));
+      zcls = g->ws_zcls.as<int32_t>();
+      zcls_val = reinterpret_cast<T*>(reinterpret_cast<char*>(g->ws_zcls.p) + ((static_cast<size_t>(N) * 4 + 255) & ~size_t(255)));
+      ND_HIP(hipMemsetAsync(zcls, 0xFF, static_cast<size_t>(N) * 4, st));
+      ND_HIP(hipMemsetAsync(zcls_val, 0, nc * kp * sizeof(T), st));
+      hipLaunchKernelGGL(k_zcls, dim3(grid_for(job.motifs->n_classes, kBlock)), dim3(kBlock), 0, st,
+                         job.motifs->class_ptr, job.motifs->members, job.motifs->n_classes, in->inv, zcls);
+      ND_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_project<T>, dim3(grid_for(job.motifs->n_classes * kb, kBlock)), dim3(kBlock), 0, st,
+                       job.motifs->class_ptr, job.motifs->members, job.motifs->n_classes, kp, kb, in->row_ptr,
+                       in->inv, Z, A, zcls_val);
+    ND_LAUNCH_CHECK();
+  }
+  StepArgs a{};
+  a.row_ptr = in->row_ptr;
+  a.col = in->col;
+  a.perm = in->perm;
+  a.n = N;
+  a.n_bins = sc->n_bins;
+  for (int b = 0; b <= kMaxBins; ++b) {
+    a.bin_row_start[b] = sc->bin_row_start[b];
+    a.bin_item_start[b] = sc->bin_item_start[b];
+    if (b < kMaxBins) a.bin_log2p[b] = sc->bin_log2p[b];
+  }
+  a.n_chunks = sc->n_chunks;
+  a.n_items = sc->n_items;
+  a.split_chunk_ptr = sc->split_chunk_ptr;
+  a.chunk_owner = sc->chunk_owner;
+  a.chunk_nnz = sc->chunk_nnz;
+  a.n_split = sc->n_split;
+  a.split_blocks = split_blocks;
+  a.slot_nnz = sc->slot_nnz;
+  a.zmode = zmode;
+  a.seed = job.seed;
+  a.j0 = j0;
+  a.zcls = zcls;
+  a.zcls_val = zcls_val;
+  a.chunk_part = g->ws_chunk.p;
+  a.z = Z;
+  a.kp = kp;
+  a.k_batch = kb;
+  a.inv_k = 1.0 / static_cast<double>(job.k);
+  a.ldos = job.ldos;
+  a.ldos_sq = job.ldos_sq;
+  a.ld = M;
+  a.accumulate = j0 > 0 ? 1 : 0;
+  a.cv_g = job.cv_g;
+  bs.kp = kp;
+  bs.L = L;
+  bs.grid = grid;
+  bs.split_blocks = split_blocks;
+  bs.zmode = zmode;
+  bs.slots = slots;
+  bs.Z = Z;
+  bs.A = A;
+  bs.B = B;
+  bs.a = a;
+  return ND_OK;
 }
 
 template <typename T>
@@ -887,20 +1024,13 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
   const int bmax = max_block_probes();
   for (int j0 = 0; j0 < job.k; j0 += bmax) {
     const int kb = job.k - j0 < bmax ? job.k - j0 : bmax;
-    const int kp = pow2_at_least(kb < PPL ? PPL : kb);
-    const int L = kp * static_cast<int>(sizeof(T)) / 16;
-    Schedule* sc = nullptr;
-    ND_CHECK(get_schedule(g, L, st, &sc));
-    Internal* in = g->internal.get();
-    const size_t blk = static_cast<size_t>(N) * kp * sizeof(T);
-    ND_CHECK(g->ws_state.ensure(3 * blk));
-    ND_CHECK(g->ws_chunk.ensure(static_cast<size_t>(sc->n_chunks > 0 ? sc->n_chunks : 1) * kp * sizeof(double)));
-    T* Z = g->ws_state.as<T>();
-    T* A = Z + static_cast<int64_t>(N) * kp;
-    T* B = A + static_cast<int64_t>(N) * kp;
-    const int grid = grid_for(sc->n_items > 0 ? sc->n_items : 1, kWavesPerBlock, step_grid<T>(L));
-    const int split_blocks = sc->n_split > 0 ? grid_for(sc->n_split, kWavesPerBlock, grid) : 0;
-    const int64_t slots = static_cast<int64_t>(grid) + split_blocks;
+    BlockSetup<T> bs;
+    ND_CHECK(setup_block<T>(g, job, j0, kb, st, bs));
+    const int kp = bs.kp, L = bs.L, grid = bs.grid, zmode = bs.zmode;
+    const int64_t slots = bs.slots;
+    T* A = bs.A;
+    T* B = bs.B;
+    StepArgs& a = bs.a;
     const int NSd = job.doubling ? 2 : 1;          // sums per probe of the step launches
     const int64_t per_step = slots * kp * NSd;
     int R = static_cast<int>((int64_t(64) << 20) / (per_step * 8));
@@ -908,67 +1038,6 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     if (R > last + 1) R = last + 1;
     ND_CHECK(g->ws_partial.ensure(static_cast<size_t>(R) * per_step * sizeof(double)));
     double* partial = g->ws_partial.as<double>();
-
-    hipLaunchKernelGGL(k_probes<T>, dim3(grid_for(N * kp, kBlock)), dim3(kBlock), 0, st, N, kp, kb,
-                       static_cast<int64_t>(j0), job.seed, job.gaussian ? 1 : 0, in->row_ptr, in->perm, Z, A);
-    ND_LAUNCH_CHECK();
-    // Rademacher rows are regenerated inside the step kernels (no probe-block
-    // reads); the projected rows of twin classes come from a small table
-    const int zmode = (!job.gaussian && !probe_buffer_forced()) ? 1 : 0;
-    const bool filt = job.motifs && job.motifs->n_classes > 0;
-    int32_t* zcls = nullptr;
-    T* zcls_val = nullptr;
-    if (filt) {
-      if (zmode) {
-        const size_t nc = static_cast<size_t>(job.motifs->n_classes);
-        ND_CHECK(g->ws_zcls.ensure(static_cast<size_t>(N) * 4 + 256 + nc * kp * sizeof(T)));
-        zcls = g->ws_zcls.as<int32_t>();
-        zcls_val = reinterpret_cast<T*>(reinterpret_cast<char*>(g->ws_zcls.p) + ((static_cast<size_t>(N) * 4 + 255) & ~size_t(255)));
-        ND_HIP(hipMemsetAsync(zcls, 0xFF, static_cast<size_t>(N) * 4, st));
-        ND_HIP(hipMemsetAsync(zcls_val, 0, nc * kp * sizeof(T), st));
-        hipLaunchKernelGGL(k_zcls, dim3(grid_for(job.motifs->n_classes, kBlock)), dim3(kBlock), 0, st,
-                           job.motifs->class_ptr, job.motifs->members, job.motifs->n_classes, in->inv, zcls);
-        ND_LAUNCH_CHECK();
-      }
-      hipLaunchKernelGGL(k_project<T>, dim3(grid_for(job.motifs->n_classes * kb, kBlock)), dim3(kBlock), 0, st,
-                         job.motifs->class_ptr, job.motifs->members, job.motifs->n_classes, kp, kb, in->row_ptr,
-                         in->inv, Z, A, zcls_val);
-      ND_LAUNCH_CHECK();
-    }
-    StepArgs a{};
-    a.row_ptr = in->row_ptr;
-    a.col = in->col;
-    a.perm = in->perm;
-    a.n = N;
-    a.n_bins = sc->n_bins;
-    for (int b = 0; b <= kMaxBins; ++b) {
-      a.bin_row_start[b] = sc->bin_row_start[b];
-      a.bin_item_start[b] = sc->bin_item_start[b];
-      if (b < kMaxBins) a.bin_log2p[b] = sc->bin_log2p[b];
-    }
-    a.n_chunks = sc->n_chunks;
-    a.n_items = sc->n_items;
-    a.split_chunk_ptr = sc->split_chunk_ptr;
-    a.chunk_owner = sc->chunk_owner;
-    a.chunk_nnz = sc->chunk_nnz;
-    a.n_split = sc->n_split;
-    a.split_blocks = split_blocks;
-    a.slot_nnz = sc->slot_nnz;
-    a.zmode = zmode;
-    a.seed = job.seed;
-    a.j0 = j0;
-    a.zcls = zcls;
-    a.zcls_val = zcls_val;
-    a.chunk_part = g->ws_chunk.p;
-    a.z = Z;
-    a.kp = kp;
-    a.k_batch = kb;
-    a.inv_k = 1.0 / static_cast<double>(job.k);
-    a.ldos = job.ldos;
-    a.ldos_sq = job.ldos_sq;
-    a.ld = M;
-    a.accumulate = j0 > 0 ? 1 : 0;
-    a.cv_g = job.cv_g;
     const double inv_n = 1.0 / static_cast<double>(N);
     for (int m = 0; m <= last; ++m) {
       a.m = m;
@@ -1045,6 +1114,214 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
   return ND_OK;
 }
 
+// ---------------------------------------------------------------- Lanczos
+// Gauss quadrature and Lanczos (Sec. 3.2) on the same sparse product: per
+// probe j, v_1 = z_j / |z_j|, w = H v_k - beta_{k-1} v_{k-1},
+// alpha_k = <v_k, w>, w -= alpha_k v_k, beta_k = |w|, v_{k+1} = w / beta_k.
+// Vectors are kept in the form X = D^{-1/2} v like the Chebyshev state, and
+// unnormalized: the stored current and previous vectors carry per-probe
+// scales (lz[0][j], and beta_{k-1} times the previous scale in lz[1][j]).
+
+// alpha_k is already reduced; W -= alpha_k c1 X_cur and per-probe sums of
+// d W^2 (the square of beta_k) into block partials.  Thread t of the grid
+// handles 16-byte slice t % L of rows t / L, ...
+template <typename T, int L>
+__global__ __launch_bounds__(kBlock) void k_lanczos_update(int64_t n, int kp, int k_batch,
+                                                           const int64_t* __restrict__ row_ptr, T* __restrict__ W,
+                                                           const T* __restrict__ X, const double* __restrict__ lz,
+                                                           const double* __restrict__ alpha, int64_t ld_alpha,
+                                                           double* __restrict__ partial) {
+  constexpr int PPL = 16 / sizeof(T);
+  __shared__ double s_mom[PPL][kBlock];
+#pragma unroll
+  for (int c = 0; c < PPL; ++c) s_mom[c][threadIdx.x] = 0.0;
+  const int q = threadIdx.x % L;
+  double coef[PPL];
+#pragma unroll
+  for (int c = 0; c < PPL; ++c) {
+    const int j = q * PPL + c;
+    coef[c] = j < k_batch ? alpha[j * ld_alpha] * lz[j] : 0.0;
+  }
+  const int64_t total = n * L;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int64_t r = t / L;
+    T w[PPL], x[PPL];
+    load16<T>(W + r * kp + q * PPL, w);
+    load16<T>(X + r * kp + q * PPL, x);
+    const double d = static_cast<double>(row_ptr[r + 1] - row_ptr[r]);
+#pragma unroll
+    for (int c = 0; c < PPL; ++c) {
+      w[c] = static_cast<T>(static_cast<double>(w[c]) - coef[c] * static_cast<double>(x[c]));
+      s_mom[c][threadIdx.x] += d * static_cast<double>(w[c]) * static_cast<double>(w[c]);
+    }
+    store16<T>(W + r * kp + q * PPL, w);
+  }
+  StepArgs b{};
+  b.kp = kp;
+  b.partial = partial;
+  block_partials<T, L, 1>(b, s_mom);
+}
+
+// Per-probe scales before the first step: c1 = 1/|z|, c2 = 0.
+__global__ void k_lanczos_init(int k_batch, int kp, double n, const double* __restrict__ norm2, double* __restrict__ lz,
+                               int32_t* __restrict__ active) {
+  const int j = threadIdx.x;
+  if (j >= kp) return;
+  const double z2 = j < k_batch ? norm2[j] * n : 0.0;
+  const bool on = z2 > 0.0;
+  lz[j] = on ? 1.0 / sqrt(z2) : 0.0;
+  lz[kp + j] = 0.0;
+  active[j] = on ? 1 : 0;
+}
+
+// After step k: beta_k = sqrt(sum d W^2); the next current vector is W with
+// scale 1/beta_k, the next previous one X_cur with coefficient beta_k c1.
+// A probe whose beta falls to `tol` or below (an invariant subspace: the
+// Gauss rule is exact) stops; its remaining coefficients are 0 and n_steps
+// records k + 1.
+__global__ void k_lanczos_scalars(int k_batch, int kp, int k, double tol, const double* __restrict__ beta2,
+                                  double* __restrict__ lz, int32_t* __restrict__ active, double* __restrict__ beta,
+                                  int64_t ld_beta, int32_t* __restrict__ n_steps) {
+  const int j = threadIdx.x;
+  if (j >= k_batch) return;
+  const double b = sqrt(beta2[j] > 0.0 ? beta2[j] : 0.0);
+  const bool was = active[j] != 0;
+  const bool on = was && b > tol;
+  beta[j * ld_beta] = on ? b : 0.0;
+  const double c1 = lz[j];
+  lz[kp + j] = on ? b * c1 : 0.0;
+  lz[j] = on ? 1.0 / b : 0.0;
+  if (was && !on) n_steps[j] = k + 1;
+  active[j] = on ? 1 : 0;
+}
+
+template <typename T, int L>
+nd_status launch_lanczos_update(int grid, int64_t n, int kp, int kb, const int64_t* row_ptr, T* W, const T* X,
+                                const double* lz, const double* alpha, int64_t ld_alpha, double* partial,
+                                hipStream_t st) {
+  hipLaunchKernelGGL((k_lanczos_update<T, L>), dim3(grid), dim3(kBlock), 0, st, n, kp, kb, row_ptr, W, X, lz, alpha,
+                     ld_alpha, partial);
+  ND_LAUNCH_CHECK();
+  return ND_OK;
+}
+
+template <typename T>
+nd_status lanczos_update(int L, int grid, int64_t n, int kp, int kb, const int64_t* row_ptr, T* W, const T* X,
+                         const double* lz, const double* alpha, int64_t ld_alpha, double* partial, hipStream_t st) {
+  switch (L) {
+    case 1: return launch_lanczos_update<T, 1>(grid, n, kp, kb, row_ptr, W, X, lz, alpha, ld_alpha, partial, st);
+    case 2: return launch_lanczos_update<T, 2>(grid, n, kp, kb, row_ptr, W, X, lz, alpha, ld_alpha, partial, st);
+    case 4: return launch_lanczos_update<T, 4>(grid, n, kp, kb, row_ptr, W, X, lz, alpha, ld_alpha, partial, st);
+    case 8: return launch_lanczos_update<T, 8>(grid, n, kp, kb, row_ptr, W, X, lz, alpha, ld_alpha, partial, st);
+    case 16: return launch_lanczos_update<T, 16>(grid, n, kp, kb, row_ptr, W, X, lz, alpha, ld_alpha, partial, st);
+    case 32:
+      if constexpr (sizeof(T) == 8)
+        return launch_lanczos_update<T, 32>(grid, n, kp, kb, row_ptr, W, X, lz, alpha, ld_alpha, partial, st);
+      break;
+    default: break;
+  }
+  set_error("internal: unsupported lane count %d", L);
+  return ND_EUNSUPPORTED;
+}
+
+// alpha, beta: device [k][K]; norm2: device [k] (|z_j|^2 / N); n_steps:
+// device int32 [k] (K unless a probe stops early).
+template <typename T>
+nd_status run_lanczos(nd_graph* g, const MomentJob& job, int K, double* alpha, double* beta, double* norm2,
+                      int32_t* n_steps, hipStream_t st) {
+  const int64_t N = g->n;
+  const double tol = sizeof(T) == 8 ? 1e-10 : 1e-5;
+  std::vector<hipEvent_t> evs;
+  if (job.timed) {
+    g->step_ms = 0.0;
+    g->step_launches = 0;
+  }
+  struct EvFree {
+    std::vector<hipEvent_t>& e;
+    ~EvFree() {
+      for (hipEvent_t x : e) (void)hipEventDestroy(x);
+    }
+  } ev_free{evs};
+  {
+    // n_steps = K until a probe stops
+    std::vector<int32_t> ks(static_cast<size_t>(job.k), K);
+    ND_HIP(hipMemcpyAsync(n_steps, ks.data(), ks.size() * 4, hipMemcpyHostToDevice, st));
+    ND_HIP(hipStreamSynchronize(st));
+  }
+  const int bmax = max_block_probes();
+  for (int j0 = 0; j0 < job.k; j0 += bmax) {
+    const int kb = job.k - j0 < bmax ? job.k - j0 : bmax;
+    BlockSetup<T> bs;
+    ND_CHECK(setup_block<T>(g, job, j0, kb, st, bs));
+    const int kp = bs.kp, L = bs.L, grid = bs.grid;
+    StepArgs& a = bs.a;
+    const int64_t per_step = bs.slots * kp;
+    ND_CHECK(g->ws_partial.ensure(static_cast<size_t>(per_step) * sizeof(double)));
+    double* partial = g->ws_partial.as<double>();
+    // scalars: lz [2][kp], beta2 [kp], active (int32) [kp]
+    ND_CHECK(g->ws_misc.ensure(static_cast<size_t>(4 * kp) * sizeof(double)));
+    double* lz = g->ws_misc.as<double>();
+    double* beta2 = lz + 2 * kp;
+    int32_t* active = reinterpret_cast<int32_t*>(beta2 + kp);
+    Internal* in = g->internal.get();
+    // |z|^2 / N per probe: the moment-0 launch of the probe block
+    a.first = 1;
+    a.xg = nullptr;
+    a.xio = nullptr;
+    a.partial = partial;
+    ND_CHECK(launch_step<T>(L, a, grid, true, st));
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, partial, bs.slots, per_step, 1, kp, kb, 0,
+                       1.0 / static_cast<double>(N), norm2, int64_t(1), static_cast<int64_t>(j0));
+    ND_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_lanczos_init, dim3(1), dim3(64), 0, st, kb, kp, static_cast<double>(N), norm2 + j0, lz,
+                       active);
+    ND_LAUNCH_CHECK();
+    a.zmode = 3;
+    a.lz = lz;
+    for (int k = 0; k < K; ++k) {
+      a.m = k + 1;
+      a.first = (k == 0) ? 1 : 0;
+      T* cur = (k & 1) ? bs.B : bs.A;
+      T* prev = (k & 1) ? bs.A : bs.B;
+      a.xg = cur;
+      a.xio = prev;  // becomes W
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (job.timed) {
+        ND_HIP(hipEventCreate(&e0));
+        evs.push_back(e0);
+        ND_HIP(hipEventCreate(&e1));
+        evs.push_back(e1);
+        ND_HIP(hipEventRecord(e0, st));
+      }
+      ND_CHECK(launch_step<T>(L, a, grid, false, st));
+      if (job.timed) ND_HIP(hipEventRecord(e1, st));
+      hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, partial, bs.slots, per_step, 1, kp, kb, k,
+                         1.0, alpha, static_cast<int64_t>(K), static_cast<int64_t>(j0));
+      ND_LAUNCH_CHECK();
+      if (k == K - 1) break;
+      ND_CHECK(lanczos_update<T>(L, grid, N, kp, kb, in->row_ptr, prev, cur, lz, alpha + static_cast<int64_t>(j0) * K + k,
+                                 K, partial, st));
+      hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, partial, static_cast<int64_t>(grid),
+                         per_step, 1, kp, kb, 0, 1.0, beta2, int64_t(1), int64_t(0));
+      ND_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_lanczos_scalars, dim3(1), dim3(64), 0, st, kb, kp, k, tol, beta2, lz, active,
+                         beta + static_cast<int64_t>(j0) * K + k, static_cast<int64_t>(K), n_steps + j0);
+      ND_LAUNCH_CHECK();
+    }
+  }
+  if (job.timed) {
+    ND_HIP(hipStreamSynchronize(st));
+    for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+      float ms = 0.f;
+      ND_HIP(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
+      g->step_ms += ms;
+      g->step_launches++;
+    }
+  }
+  return ND_OK;
+}
+
 nd_status check_common(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes, int32_t n_moments,
                        uint32_t flags, const char* who) {
   ND_REQUIRE(g != nullptr, "%s: graph is NULL", who);
@@ -1061,6 +1338,26 @@ nd_status check_common(const nd_graph* g, const nd_motifs* motifs, int32_t n_pro
 }
 
 }  // namespace
+
+nd_status lanczos_coefficients(nd_graph* g, const nd_motifs* motifs, int32_t n_probes, int32_t n_steps, uint64_t seed,
+                               uint32_t flags, double* alpha, double* beta, double* norm2, int32_t* steps,
+                               hipStream_t st) {
+  MomentJob job;
+  job.motifs = motifs;
+  job.k = n_probes;
+  job.M = n_steps;
+  job.seed = seed;
+  job.gaussian = (flags & ND_PROBE_GAUSSIAN) != 0;
+  job.timed = (flags & ND_TIME_STEPS) != 0;
+  if (flags & ND_STATE_FP64) return run_lanczos<double>(g, job, n_steps, alpha, beta, norm2, steps, st);
+  return run_lanczos<float>(g, job, n_steps, alpha, beta, norm2, steps, st);
+}
+
+nd_status check_moment_args(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes, int32_t n_moments,
+                            uint32_t flags, const char* who) {
+  return check_common(g, motifs, n_probes, n_moments, flags, who);
+}
+
 }  // namespace nd
 
 // ====================================================================== C ABI
