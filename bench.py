@@ -40,9 +40,11 @@ UNIT = "G(nnz·probe·moment)/s"
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(n: int, nnz: int, k: int, ldos: bool, state_bytes: int = 4) -> int:
-    """Compulsory HBM traffic of one sparse step (one kernel launch)."""
-    b = 4 * nnz + 8 * (n + 1) + 4 * n + 3 * state_bytes * k * n
+def algorithmic_bytes(n: int, nnz: int, k: int, ldos: bool, state_bytes: int = 4, own_row: bool = False) -> int:
+    """Compulsory HBM traffic of one sparse step (one kernel launch); the
+    doubling and Lanczos steps also read each row's own entry of the gathered
+    block (own_row)."""
+    b = 4 * nnz + 8 * (n + 1) + 4 * n + (4 if own_row else 3) * state_bytes * k * n
     if ldos:
         b += 8 * n
     return b
@@ -297,6 +299,9 @@ def main():
     ap.add_argument("--cv-target-probes", type=int, default=1024)
     ap.add_argument("--cv-steps", type=int, default=3000)
     ap.add_argument("--no-filter", action="store_true", help="skip twin filtering (ba1m_twins)")
+    ap.add_argument("--gql", type=int, default=0, metavar="K",
+                    help="global-DOS workloads: Gauss quadrature and Lanczos with K steps instead of KPM "
+                         "(the rule's Chebyshev moments feed the same reconstruction)")
     ap.add_argument("--doubling", action="store_true",
                     help="global-DOS workloads: moments from floor(M/2) sparse products (doubling identities); "
                          "the rate still counts the products actually done")
@@ -307,6 +312,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.gql and args.doubling:
+        ap.error("--gql and --doubling are exclusive")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the hot path shards by probes, "
               "see the design notes); --gpus must be 1", file=sys.stderr)
@@ -359,6 +366,14 @@ def main():
             nd.nd_ldos_moments(g, motifs, k, M, args.seed, flags, out["ldos"], mu=out["mu"])
             nd.nd_reconstruct(out["ldos"], g.n, M, nd.ND_KERNEL_JACKSON, (), 50, -1.0, 1.0, out["pdos"])
             kern = nd.ND_KERNEL_JACKSON | (nd.ND_SPIKES_IN_MOMENTS if spikes else 0)
+        elif args.gql:
+            K = args.gql
+            if "nodes" not in out:
+                out["nodes"] = torch.empty(k * K, dtype=f64, device="cuda")
+                out["weights"] = torch.empty(k * K, dtype=f64, device="cuda")
+            nd.nd_gql(g, motifs, k, K, args.seed, flags, out["nodes"], out["weights"])
+            nd.nd_gql_density(out["nodes"], out["weights"], k, K, M, out["mu"])
+            kern = nd.ND_KERNEL_JACKSON
         else:
             if args.doubling:
                 flags |= nd.ND_MOMENT_DOUBLING
@@ -393,7 +408,7 @@ def main():
     work = nnz * k * products
     value = work / (ms_step * 1e-3) / 1e9
     avg_launch_ms = kern_ms / max(kern_n, 1)
-    b_launch = algorithmic_bytes(n, nnz, k, W.ldos)
+    b_launch = algorithmic_bytes(n, nnz, k, W.ldos, own_row=bool(not W.ldos and (args.doubling or args.gql)))
     achieved = b_launch / (avg_launch_ms * 1e-3) / 1e9
     traffic = profiled_traffic(args.workload)
     copy_gbs = copy_bandwidth_gbs()
@@ -415,7 +430,8 @@ def main():
                    "probes": k, "moments": M, "twin_filter": use_filter, "twin_classes": n_cls,
                    "ldos": W.ldos, "state": "fp32 recurrence, fp64 compensated moment sums",
                    "sparse_products_per_probe": products,
-                   "doubling": bool(args.doubling and not W.ldos)},
+                   "doubling": bool(args.doubling and not W.ldos and not args.gql),
+                   "method": "gql K=%d" % args.gql if args.gql and not W.ldos else "kpm"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_GBs": round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1) if traffic else None,

@@ -219,6 +219,20 @@ nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
                           const float* cv_g, double* ldos, double* ldos_sq, double* mu,
                           void* stream);
 
+/* Exact PDOS moments of selected nodes (eqn pdoscoeff): for each listed node
+ * v, pdos[i][m] = T_m(H)_vv = e_v^T T_m(H) e_v, from the same recurrence run
+ * on unit probes (64 nodes per block of the probe block), m = 0..M-1.  The
+ * paper obtains accurate PDOS for a node subset by nested dissection
+ * (Sec. 3.3, Algorithm 1); this computes the same quantity directly, at the
+ * cost of one probe column per node, with no partitioning.
+ *   nodes   device int32 [n_nodes], compact node ids (duplicates allowed)
+ *   flags   optionally ND_STATE_FP64, ND_TIME_STEPS
+ *   pdos    device double [n_nodes][n_moments]
+ * Synchronises `stream` once to validate the ids (ND_EINVAL when out of
+ * range). */
+nd_status nd_pdos_nodes(const nd_graph* g, const int32_t* nodes, int32_t n_nodes, int32_t n_moments, uint32_t flags,
+                        double* pdos, void* stream);
+
 /* --------------------------------------------------------------- GQL */
 
 /* Gauss quadrature and Lanczos (Sec. 3.2).  For every probe z_j (the same

@@ -37,7 +37,7 @@ EXPORTS = (
     "nd_graph_free",
     "nd_motif_filter", "nd_motif_info", "nd_motif_export", "nd_motif_export_lambda", "nd_motifs_free",
     "nd_make_probes",
-    "nd_cheb_moments", "nd_ldos_moments", "nd_gql", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_column_stats",
+    "nd_cheb_moments", "nd_ldos_moments", "nd_pdos_nodes", "nd_gql", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_column_stats",
     "nd_mlp_forward", "nd_mlp_grad", "nd_adam_step", "nd_last_error",
 )
 
@@ -82,17 +82,16 @@ _sig("nd_motifs_free", [_vp], None)
 _sig("nd_make_probes", [_vp, _vp, _i32, _u64, _u32, _vp, _vp])
 _sig("nd_cheb_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp])
 _sig("nd_ldos_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp, _vp])
+_sig("nd_pdos_nodes", [_vp, _vp, _i32, _i32, _u32, _vp, _vp])
 _sig("nd_gql", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("nd_gql_density", [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _dbl, _dbl, _vp, _vp])
 _sig("nd_reconstruct", [_vp, _i64, _i32, _u32, _vp, _vp, _i32, _i32, _dbl, _dbl, _vp, _i32, _vp, _vp])
 _sig("nd_last_error", [], ctypes.c_char_p)
-_HAS_CV = hasattr(_lib, "nd_node_features")
-if _HAS_CV:
-    _sig("nd_node_features", [_vp, _vp, _vp, _vp, _vp])
-    _sig("nd_column_stats", [_vp, _i64, _i32, _vp, _vp, _vp])
-    _sig("nd_mlp_forward", [_vp, _vp, _i64, _i32, _vp, _vp])
-    _sig("nd_mlp_grad", [_vp, _vp, _vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp])
-    _sig("nd_adam_step", [_vp, _vp, _vp, _vp, _i64, _i32, _flt, _vp])
+_sig("nd_node_features", [_vp, _vp, _vp, _vp, _vp])
+_sig("nd_column_stats", [_vp, _i64, _i32, _vp, _vp, _vp])
+_sig("nd_mlp_forward", [_vp, _vp, _i64, _i32, _vp, _vp])
+_sig("nd_mlp_grad", [_vp, _vp, _vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp])
+_sig("nd_adam_step", [_vp, _vp, _vp, _vp, _i64, _i32, _flt, _vp])
 
 
 def _check(status: int, where: str):
@@ -284,6 +283,15 @@ def nd_ldos_moments(g: Graph, motifs, n_probes: int, n_moments: int, seed: int, 
                                 _stream(stream)), "nd_ldos_moments")
 
 
+def nd_pdos_nodes(g: Graph, nodes, n_moments: int, flags: int, pdos, stream=None):
+    """Exact PDOS moments of the nodes in the device int32 tensor `nodes`."""
+    import torch
+    n = int(nodes.numel()) if nodes is not None else 0
+    pn = _dev(nodes, torch.int32, n, "nodes")
+    pp = _dev(pdos, torch.float64, n * n_moments, "pdos")
+    _check(_lib.nd_pdos_nodes(g.handle, pn, n, n_moments, flags, pp, _stream(stream)), "nd_pdos_nodes")
+
+
 def nd_gql(g: Graph, motifs, n_probes: int, n_steps: int, seed: int, flags: int, nodes, weights, steps=None,
            alpha=None, beta=None, stream=None):
     import torch
@@ -331,14 +339,8 @@ def n_params(n_out: int) -> int:
     return N_FEAT * WIDTH + WIDTH + WIDTH * WIDTH + WIDTH + WIDTH * n_out + n_out
 
 
-def _need_cv():
-    if not _HAS_CV:
-        raise NDError(ND_EUNSUPPORTED, "control variate", "this libnd build has no control-variate kernels")
-
-
 def nd_node_features(g: Graph, feat, mean=None, std=None, stream=None):
     import torch
-    _need_cv()
     _check(_lib.nd_node_features(g.handle, _dev(mean, torch.float32, N_FEAT, "mean"),
                                  _dev(std, torch.float32, N_FEAT, "std"), _dev(feat, torch.float32, g.n * N_FEAT, "feat"),
                                  _stream(stream)), "nd_node_features")
@@ -346,7 +348,6 @@ def nd_node_features(g: Graph, feat, mean=None, std=None, stream=None):
 
 def nd_column_stats(x, n_rows: int, n_cols: int, mean, std, stream=None):
     import torch
-    _need_cv()
     _check(_lib.nd_column_stats(_dev(x, torch.float32, n_rows * n_cols, "x"), n_rows, n_cols,
                                 _dev(mean, torch.float32, n_cols, "mean"), _dev(std, torch.float32, n_cols, "std"),
                                 _stream(stream)), "nd_column_stats")
@@ -354,7 +355,6 @@ def nd_column_stats(x, n_rows: int, n_cols: int, mean, std, stream=None):
 
 def nd_mlp_forward(params, feat, n: int, n_out: int, g, stream=None):
     import torch
-    _need_cv()
     _check(_lib.nd_mlp_forward(_dev(params, torch.float32, n_params(n_out), "params"),
                                _dev(feat, torch.float32, n * N_FEAT, "feat"), n, n_out,
                                _dev(g, torch.float32, n * n_out, "g"), _stream(stream)), "nd_mlp_forward")
@@ -362,7 +362,6 @@ def nd_mlp_forward(params, feat, n: int, n_out: int, g, stream=None):
 
 def nd_mlp_grad(params, feat, target, ld_target: int, idx, n: int, n_out: int, grad, loss, stream=None):
     import torch
-    _need_cv()
     rows = feat.numel() // N_FEAT
     if idx is not None:
         pidx = _dev(idx, torch.int32, n, "idx")
@@ -381,7 +380,6 @@ def nd_mlp_grad(params, feat, target, ld_target: int, idx, n: int, n_out: int, g
 
 def nd_adam_step(params, m, v, grad, n_params_: int, t: int, lr: float, stream=None):
     import torch
-    _need_cv()
     _check(_lib.nd_adam_step(_dev(params, torch.float32, n_params_, "params"), _dev(m, torch.float32, n_params_, "m"),
                              _dev(v, torch.float32, n_params_, "v"), _dev(grad, torch.float32, n_params_, "grad"),
                              n_params_, t, lr, _stream(stream)), "nd_adam_step")

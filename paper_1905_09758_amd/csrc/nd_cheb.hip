@@ -609,6 +609,18 @@ __global__ __launch_bounds__(kBlock) void k_probes(int64_t n, int ld, int k_batc
   }
 }
 
+// Unit probes: column j of the (zeroed) block is e_{node_j}: Z = 1 and
+// X_0 = 1/sqrt(d) at the node's internal row.
+template <typename T>
+__global__ void k_unit_probes(int k_batch, int ld, const int32_t* __restrict__ nodes, const int32_t* __restrict__ inv,
+                              const int64_t* __restrict__ row_ptr, T* __restrict__ Z, T* __restrict__ X0) {
+  const int j = threadIdx.x;
+  if (j >= k_batch) return;
+  const int64_t r = inv[nodes[j]];
+  Z[r * ld + j] = T(1);
+  X0[r * ld + j] = static_cast<T>(1.0 / sqrt(static_cast<double>(row_ptr[r + 1] - row_ptr[r])));
+}
+
 // Twin projection Z <- P P^T Z (Sec. 3.4): each class's rows replaced by the
 // class mean (fp64 sum in member order).  Members of a class share their
 // neighbourhood and hence their degree.  Member node i lives in row inv[i]
@@ -842,6 +854,7 @@ struct MomentJob {
   int n_spikes = 0;                // (added to mu as sum_s w_s T_m(lambda_s))
   bool timed = false;
   bool doubling = false;  // global moments from products of Y_s (about M/2 launches)
+  const int32_t* unit_nodes = nullptr;  // device [k]: probe j is the unit vector of node unit_nodes[j]
 };
 
 template <typename T, int L, int ZM>
@@ -922,12 +935,18 @@ nd_status setup_block(nd_graph* g, const MomentJob& job, int j0, int kb, hipStre
   const int split_blocks = sc->n_split > 0 ? grid_for(sc->n_split, kWavesPerBlock, grid) : 0;
   const int64_t slots = static_cast<int64_t>(grid) + split_blocks;
 
-  hipLaunchKernelGGL(k_probes<T>, dim3(grid_for(N * kp, kBlock)), dim3(kBlock), 0, st, N, kp, kb,
-                     static_cast<int64_t>(j0), job.seed, job.gaussian ? 1 : 0, in->row_ptr, in->perm, Z, A);
+  if (job.unit_nodes) {
+    ND_HIP(hipMemsetAsync(Z, 0, 2 * blk, st));  // Z and A = X_0
+    hipLaunchKernelGGL(k_unit_probes<T>, dim3(1), dim3(64), 0, st, kb, kp, job.unit_nodes + j0, in->inv, in->row_ptr,
+                       Z, A);
+  } else {
+    hipLaunchKernelGGL(k_probes<T>, dim3(grid_for(N * kp, kBlock)), dim3(kBlock), 0, st, N, kp, kb,
+                       static_cast<int64_t>(j0), job.seed, job.gaussian ? 1 : 0, in->row_ptr, in->perm, Z, A);
+  }
   ND_LAUNCH_CHECK();
   // Rademacher rows are regenerated inside the step kernels (no probe-block
   // reads); the projected rows of twin classes come from a small table
-  const int zmode = (!job.gaussian && !probe_buffer_forced()) ? 1 : 0;
+  const int zmode = (!job.gaussian && !job.unit_nodes && !probe_buffer_forced()) ? 1 : 0;
   const bool filt = job.motifs && job.motifs->n_classes > 0;
   int32_t* zcls = nullptr;
   T* zcls_val = nullptr;
@@ -1038,7 +1057,8 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     if (R > last + 1) R = last + 1;
     ND_CHECK(g->ws_partial.ensure(static_cast<size_t>(R) * per_step * sizeof(double)));
     double* partial = g->ws_partial.as<double>();
-    const double inv_n = 1.0 / static_cast<double>(N);
+    // unit probes: z^T T_m(H) z is the PDOS moment itself, no 1/N
+    const double inv_n = job.unit_nodes ? 1.0 : 1.0 / static_cast<double>(N);
     for (int m = 0; m <= last; ++m) {
       a.m = m;
       // ring position of this launch's partials; with doubling, moment 0 is
@@ -1416,6 +1436,31 @@ nd_status nd_cheb_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
   nd_graph* gm = const_cast<nd_graph*>(g);
   if (flags & ND_STATE_FP64) return nd::run_moments<double>(gm, job, nd::as_stream(stream));
   return nd::run_moments<float>(gm, job, nd::as_stream(stream));
+}
+
+nd_status nd_pdos_nodes(const nd_graph* g, const int32_t* nodes, int32_t n_nodes, int32_t n_moments, uint32_t flags,
+                        double* pdos, void* stream) {
+  nd::clear_error();
+  ND_CHECK(nd::check_common(g, nullptr, n_nodes, n_moments, flags, "nd_pdos_nodes"));
+  ND_REQUIRE((flags & ~(ND_STATE_FP64 | ND_TIME_STEPS)) == 0, "nd_pdos_nodes: flags 0x%x (only ND_STATE_FP64, "
+             "ND_TIME_STEPS apply)", flags);
+  ND_REQUIRE(nodes != nullptr && pdos != nullptr, "nd_pdos_nodes: nodes/pdos are NULL");
+  hipStream_t st = nd::as_stream(stream);
+  {
+    std::vector<int32_t> h(static_cast<size_t>(n_nodes));
+    ND_HIP(hipMemcpyAsync(h.data(), nodes, h.size() * 4, hipMemcpyDeviceToHost, st));
+    ND_HIP(hipStreamSynchronize(st));
+    for (int32_t v : h) ND_REQUIRE(v >= 0 && v < g->n, "nd_pdos_nodes: node id %d not in [0, %lld)", v, (long long)g->n);
+  }
+  nd::MomentJob job;
+  job.k = n_nodes;
+  job.M = n_moments;
+  job.mu_pp = pdos;
+  job.unit_nodes = nodes;
+  job.timed = (flags & ND_TIME_STEPS) != 0;
+  nd_graph* gm = const_cast<nd_graph*>(g);
+  if (flags & ND_STATE_FP64) return nd::run_moments<double>(gm, job, st);
+  return nd::run_moments<float>(gm, job, st);
 }
 
 nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes, int32_t n_moments,

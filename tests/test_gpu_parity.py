@@ -426,3 +426,28 @@ def test_errors(nd):
     assert empty.n == 0 and empty.nnz == 0
     with pytest.raises(nd.NDError):
         nd.nd_cheb_moments(empty, None, 4, 4, 1, 0, mu)
+
+
+@pytest.mark.parametrize("state", ["fp32", "fp64"])
+def test_pdos_nodes_exact(nd, state):
+    """Unit probes give the PDOS moments themselves: against the
+    eigendecomposition, for 70 nodes (two probe blocks) including the
+    highest-degree node, a leaf and a repeated id."""
+    import torch
+    n, s, d = sg.barabasi_albert(1500, 2, seed=3, twin_pairs=20)
+    g_or = og.build_csr(n, s, d)
+    g = nd.nd_build_csr(n, s, d)
+    M = 60
+    _, l_x = kpm.exact_moments_eig(og.normalized_adjacency(g_or), M)
+    rng = np.random.default_rng(2)
+    sel = np.concatenate([[int(np.argmax(g_or.deg)), int(np.argmin(g_or.deg))],
+                          rng.choice(g_or.n, 67, replace=False), [5]]).astype(np.int32)
+    pd = _zeros(sel.size * M, torch.float64)
+    flags = nd.ND_STATE_FP64 if state == "fp64" else 0
+    nd.nd_pdos_nodes(g, _t(sel), M, flags, pd)
+    got = pd.cpu().numpy().reshape(sel.size, M)
+    assert np.all(got[:, 0] == 1.0)
+    tol = TOL_FP64 if state == "fp64" else 1e-5
+    assert np.max(np.abs(got - l_x[sel])) < tol
+    with pytest.raises(nd.NDError):
+        nd.nd_pdos_nodes(g, _t(np.array([g.n], np.int32)), M, 0, pd)
