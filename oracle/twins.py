@@ -17,6 +17,15 @@ C of such nodes contributes |C| - 1 eigenvalues at -1/d (the spikes at -1/2,
 -1/3, ... of the paper's spectra).  A node cannot have twins of both kinds
 (an open twin j and a closed twin k would force k ~ j, hence j in N[i]).
 
+Pendant chains (the figure's panel at +-1/sqrt(2)): c >= 2 paths E - B - A
+hanging off the same node E (deg B = 2, deg A = 1).  On the differences
+between copies H couples each A to its B with 1/sqrt(2), so the
+2(c - 1)-dimensional space of differences carries c - 1 eigenvalues at
++1/sqrt(2) and c - 1 at -1/sqrt(2).  They are handled as two classes (the
+A's and the B's) whose projection is again the class mean; each class holds
+half of the pair, written as the signature [(+h, 1/2), (-h, 1/2)], and the
+diagonal of T_m(H) on the removed space is (1 - 1/c)(T_m(h) + T_m(-h))/2.
+
 The paper detects them with a random hash w = Hz (equal w_i = w_j with high
 probability means equal neighbourhoods); here the oracle groups nodes by the
 exact key "sorted neighbour list" (a dict), so the partition is exact.
@@ -71,12 +80,57 @@ def class_eigenvalue(g, cls) -> float:
     return 0.0
 
 
+def signature(sig):
+    """A class's removed eigenvalues as [(lambda, fraction)]: a plain number is
+    one eigenvalue taking all |C| - 1 removed dimensions."""
+    if isinstance(sig, (int, float, np.floating)):
+        return [(float(sig), 1.0)]
+    return [(float(l), float(f)) for l, f in sig]
+
+
+def chain_classes(g) -> list:
+    """Pendant chains grouped by their attachment node: pairs (B-class,
+    A-class), members ascending, for every node E with >= 2 paths E - B - A
+    (deg B = 2, deg A = 1, B's other neighbour E not a leaf)."""
+    deg = np.diff(g.row_ptr)
+    groups = {}
+    for b in range(g.n):
+        if deg[b] != 2:
+            continue
+        u, v = (int(x) for x in g.neighbors(b))
+        if (deg[u] == 1) == (deg[v] == 1):
+            continue
+        a, e = (u, v) if deg[u] == 1 else (v, u)
+        groups.setdefault(e, []).append((b, a))
+    out = []
+    for e in sorted(groups):
+        if len(groups[e]) >= 2:
+            out.append((sorted(b for b, _ in groups[e]), sorted(a for _, a in groups[e])))
+    return out
+
+
+def motif_classes(g, kinds) -> tuple:
+    """All classes of the requested kinds ("open", "closed", "chains"), in
+    canonical order (by smallest member), with their signatures."""
+    cls = []
+    for kind in ("open", "closed"):
+        if kind in kinds:
+            cls += [(c, class_eigenvalue(g, c)) for c in twin_classes(g, kind)]
+    if "chains" in kinds:
+        h = float(np.sqrt(0.5))   # 1/sqrt(2), correctly rounded
+        for cb, ca in chain_classes(g):
+            cls += [(cb, [(h, 0.5), (-h, 0.5)]), (ca, [(h, 0.5), (-h, 0.5)])]
+    cls.sort(key=lambda t: t[0][0])
+    return [c for c, _ in cls], [sgn for _, sgn in cls]
+
+
 def spikes(classes, lambdas, n: int) -> list:
-    """Point masses removed from the DOS: [(lambda, sum over classes with that
-    eigenvalue of (|C| - 1) / N)], ascending in lambda."""
+    """Point masses removed from the DOS: [(lambda, sum over classes of
+    (|C| - 1) times the class's share of that eigenvalue / N)], ascending."""
     acc = {}
-    for c, lam in zip(classes, lambdas):
-        acc[lam] = acc.get(lam, 0) + len(c) - 1
+    for c, sig in zip(classes, lambdas):
+        for lam, f in signature(sig):
+            acc[lam] = acc.get(lam, 0.0) + (len(c) - 1) * f
     return [(lam, acc[lam] / float(n)) for lam in sorted(acc)]
 
 
@@ -143,9 +197,10 @@ def cheb_at(lam: float, M: int) -> np.ndarray:
 
 def filtered_moments(H, Z: np.ndarray, M: int, classes, ldos: bool = True, lambdas=None):
     """Filtered estimates as in the module docstring, for classes whose
-    removed eigenvalues are `lambdas` (all 0, open twins, when omitted):
-        mu_m = smooth part + sum_C (|C|-1)/N T_m(lambda_C)
-        C_im = smooth part + [i in C] (1 - 1/|C|) T_m(lambda_C).
+    removed eigenvalues are `lambdas` (signatures; all 0, open twins, when
+    omitted):
+        mu_m = smooth part + sum_C (|C|-1)/N sum_s f_s T_m(lambda_s)
+        C_im = smooth part + [i in C] (1 - 1/|C|) sum_s f_s T_m(lambda_s).
     Returns (mu_full [M], mu_smooth [M], mu_pp_smooth [k][M], C [N][M] or None)."""
     from .kpm import stochastic_moments
     n = Z.shape[0]
@@ -157,6 +212,7 @@ def filtered_moments(H, Z: np.ndarray, M: int, classes, ldos: bool = True, lambd
     for lam, w in spikes(classes, lambdas, n):
         mu_full += w * cheb_at(lam, M)
     if ldos:
-        for c, lam in zip(classes, lambdas):
-            C[np.asarray(c), :] += (1.0 - 1.0 / len(c)) * cheb_at(lam, M)[None, :]
+        for c, sig in zip(classes, lambdas):
+            t = sum(f * cheb_at(lam, M) for lam, f in signature(sig))
+            C[np.asarray(c), :] += (1.0 - 1.0 / len(c)) * t[None, :]
     return mu_full, mu_s, mu_pp, C
