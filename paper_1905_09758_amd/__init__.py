@@ -26,6 +26,7 @@ ND_PROBE_RADEMACHER, ND_PROBE_GAUSSIAN, ND_STATE_FP64, ND_TIME_STEPS = 0x0, 0x1,
 ND_MOMENT_DOUBLING = 0x8
 ND_TWINS_OPEN = 0x1
 ND_TWINS_CLOSED = 0x2
+ND_CHAINS = 0x4
 ND_KERNEL_NONE, ND_KERNEL_JACKSON, ND_SPIKES_IN_MOMENTS = 0, 1, 0x10
 
 _STATUS = {ND_EINVAL: "ND_EINVAL", ND_ENOMEM: "ND_ENOMEM", ND_EDEVICE: "ND_EDEVICE",
@@ -77,7 +78,7 @@ _sig("nd_graph_free", [_vp], None)
 _sig("nd_motif_filter", [_vp, _u64, _u32, _vp, _P(_vp)])
 _sig("nd_motif_info", [_vp, _P(_i64), _P(_i64), _P(_i32), _vp, _vp])
 _sig("nd_motif_export", [_vp, _vp, _vp])
-_sig("nd_motif_export_lambda", [_vp, _vp])
+_sig("nd_motif_export_lambda", [_vp, _vp, _vp])
 _sig("nd_motifs_free", [_vp], None)
 _sig("nd_make_probes", [_vp, _vp, _i32, _u64, _u32, _vp, _vp])
 _sig("nd_cheb_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp])
@@ -247,11 +248,14 @@ def nd_motif_export(m: Motifs):
     return ptr, mem[:m.n_members]
 
 
-def nd_motif_export_lambda(m: Motifs) -> np.ndarray:
-    """Eigenvalue removed by each class: 0 (open twins) or -1/d (closed twins)."""
+def nd_motif_export_lambda(m: Motifs, paired: bool = False):
+    """Eigenvalue removed by each class: 0 (open twins), -1/d (closed twins)
+    or 1/sqrt(2) (chain classes); with paired=True also the int32 flags of
+    the classes that hold +-lambda."""
     lam = np.empty(max(m.n_classes, 1), np.float64)
-    _check(_lib.nd_motif_export_lambda(m.handle, lam.ctypes.data), "nd_motif_export_lambda")
-    return lam[:m.n_classes]
+    pr = np.empty(max(m.n_classes, 1), np.int32)
+    _check(_lib.nd_motif_export_lambda(m.handle, lam.ctypes.data, pr.ctypes.data), "nd_motif_export_lambda")
+    return (lam[:m.n_classes], pr[:m.n_classes]) if paired else lam[:m.n_classes]
 
 
 # ------------------------------------------------------------------ moments

@@ -745,10 +745,13 @@ __global__ __launch_bounds__(kBlock) void k_mu_final(const double* __restrict__ 
   }
 }
 
-// ldos[i][m] += (1 - 1/|C|) T_m(lambda_C) for every member i of a class C.
+// ldos[i][m] += (1 - 1/|C|) T_m(lambda_C) for every member i of a class C;
+// a paired class (eigenvalues +-lambda_C, half each) adds
+// (1 - 1/|C|) (T_m(lambda) + T_m(-lambda)) / 2, i.e. T_m(lambda) at even m.
 __global__ __launch_bounds__(kBlock) void k_ldos_spike(const int64_t* __restrict__ class_ptr,
                                                        const int32_t* __restrict__ members,
-                                                       const double* __restrict__ class_lambda, int64_t n_classes,
+                                                       const double* __restrict__ class_lambda,
+                                                       const int32_t* __restrict__ class_paired, int64_t n_classes,
                                                        int64_t n_members, int M, double* __restrict__ ldos) {
   for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n_members;
        p += static_cast<int64_t>(gridDim.x) * kBlock) {
@@ -759,10 +762,11 @@ __global__ __launch_bounds__(kBlock) void k_ldos_spike(const int64_t* __restrict
     }
     const double w = 1.0 - 1.0 / static_cast<double>(class_ptr[lo + 1] - class_ptr[lo]);
     const double x = class_lambda[lo];
+    const bool pair = class_paired[lo] != 0;
     double* row = ldos + static_cast<int64_t>(members[p]) * M;
     double t0 = 1.0, t1 = x;
     for (int m = 0; m < M; ++m) {
-      row[m] += w * t0;
+      if (!pair || (m & 1) == 0) row[m] += w * t0;
       const double t2 = 2.0 * x * t1 - t0;
       t0 = t1;
       t1 = t2;
@@ -1127,8 +1131,8 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
   }
   if (job.ldos && job.motifs && job.motifs->n_classes > 0) {
     hipLaunchKernelGGL(k_ldos_spike, dim3(grid_for(job.motifs->n_members, kBlock)), dim3(kBlock), 0, st,
-                       job.motifs->class_ptr, job.motifs->members, job.motifs->class_lambda, job.motifs->n_classes,
-                       job.motifs->n_members, M, job.ldos);
+                       job.motifs->class_ptr, job.motifs->members, job.motifs->class_lambda,
+                       job.motifs->class_paired, job.motifs->n_classes, job.motifs->n_members, M, job.ldos);
     ND_LAUNCH_CHECK();
   }
   return ND_OK;

@@ -187,6 +187,7 @@ struct nd_motifs {
   int64_t* class_ptr = nullptr;  // [n_classes+1]
   int32_t* members = nullptr;    // [n_members]
   double* class_lambda = nullptr;  // [n_classes] eigenvalue removed by each class
+  int32_t* class_paired = nullptr; // [n_classes] 1: the class holds +-class_lambda, half each
   // distinct removed eigenvalues (ascending) and their DOS mass sum (|C|-1)/n
   std::vector<double> spike_lambda, spike_weight;
   double* spikes_d = nullptr;    // device copy: lambdas then weights

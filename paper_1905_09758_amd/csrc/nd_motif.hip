@@ -14,6 +14,12 @@
 // and verified again, until every group is exact.  The partition is
 // independent of the seed.  A node cannot have twins of both kinds, so the
 // two passes give disjoint groups.
+//
+// Pendant chains (the motif figure's panel at +-1/sqrt(2)): nodes B of degree
+// 2 with exactly one leaf neighbour A, grouped by their other neighbour E;
+// a group of c >= 2 chains gives two classes (the B's and the A's), whose
+// differences carry c-1 eigenvalues at +1/sqrt(2) and c-1 at -1/sqrt(2).
+// Chain nodes are never twins, so all classes stay disjoint.
 #include <cstdlib>
 #include <map>
 #include <vector>
@@ -139,14 +145,64 @@ __global__ __launch_bounds__(kBlock) void k_node_labels(const int64_t* __restric
   }
 }
 
-// Merge the closed-neighbourhood labels into the open ones (disjoint).
+// Merge another pass's labels into lab (the kinds are disjoint), marking
+// the merged nodes with `kind_id` (1 closed twins, 2 pendant chains).
 __global__ __launch_bounds__(kBlock) void k_merge_labels(int32_t* __restrict__ lab, const int32_t* __restrict__ lab2,
-                                                         int64_t n, int32_t* __restrict__ closed_flag) {
+                                                         int64_t n, int kind_id, int32_t* __restrict__ kind) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     if (lab[i] < 0 && lab2[i] >= 0) {
       lab[i] = lab2[i];
-      closed_flag[i] = 1;
+      kind[i] = kind_id;
+    }
+  }
+}
+
+// Chain candidates: key = the attachment node E of B (n when B is not a
+// chain middle), payload B.
+__global__ __launch_bounds__(kBlock) void k_chain_keys(const int64_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col, int64_t n,
+                                                       uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+  for (int64_t b = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; b < n;
+       b += static_cast<int64_t>(gridDim.x) * kBlock) {
+    uint64_t k = static_cast<uint64_t>(n);
+    if (row_ptr[b + 1] - row_ptr[b] == 2) {
+      const int32_t u = col[row_ptr[b]], v = col[row_ptr[b] + 1];
+      const bool lu = row_ptr[u + 1] - row_ptr[u] == 1, lv = row_ptr[v + 1] - row_ptr[v] == 1;
+      if (lu != lv) k = static_cast<uint64_t>(lu ? v : u);
+    }
+    key[b] = k;
+    val[b] = static_cast<uint32_t>(b);
+  }
+}
+
+// The leaf of chain middle b.
+__device__ inline int32_t chain_leaf(const int64_t* row_ptr, const int32_t* col, int64_t b) {
+  const int32_t u = col[row_ptr[b]];
+  return row_ptr[u + 1] - row_ptr[u] == 1 ? u : col[row_ptr[b] + 1];
+}
+
+// Runs of equal key (sorted, B ascending within a run) of length >= 2: the
+// thread at a run's head labels the B's with the run's first B and the
+// leaves with the run's smallest leaf (one pass over each run).
+__global__ __launch_bounds__(kBlock) void k_chain_groups(const uint64_t* __restrict__ key,
+                                                         const uint32_t* __restrict__ val, int64_t n,
+                                                         const int64_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col, int32_t* __restrict__ lab) {
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
+       p += static_cast<int64_t>(gridDim.x) * kBlock) {
+    if (key[p] == static_cast<uint64_t>(n) || (p > 0 && key[p - 1] == key[p])) continue;
+    int64_t e = p;
+    while (e + 1 < n && key[e + 1] == key[p]) ++e;
+    if (e == p) continue;  // a single chain
+    int32_t amin = chain_leaf(row_ptr, col, val[p]);
+    for (int64_t t = p + 1; t <= e; ++t) {
+      const int32_t a = chain_leaf(row_ptr, col, val[t]);
+      amin = a < amin ? a : amin;
+    }
+    for (int64_t t = p; t <= e; ++t) {
+      lab[val[t]] = static_cast<int32_t>(val[p]);
+      lab[chain_leaf(row_ptr, col, val[t])] = amin;
     }
   }
 }
@@ -161,20 +217,25 @@ __global__ __launch_bounds__(kBlock) void k_leaders(const int32_t* __restrict__ 
   }
 }
 
-// Class c (classes ordered by leader node): size and removed eigenvalue
-// (0 for open twins, -1/d for closed twins of degree d).
+// Class c (classes ordered by leader node): size, removed eigenvalue (0 for
+// open twins, -1/d for closed twins of degree d, 1/sqrt(2) for chain classes,
+// which hold the pair +-1/sqrt(2) with half of the class's dimensions each)
+// and the pair flag.
 __global__ __launch_bounds__(kBlock) void k_class_info(const int32_t* __restrict__ is_leader,
                                                        const int32_t* __restrict__ cnt,
                                                        const int64_t* __restrict__ cls_of_node,
-                                                       const int32_t* __restrict__ closed_flag,
+                                                       const int32_t* __restrict__ kind,
                                                        const int64_t* __restrict__ row_ptr, int64_t n,
-                                                       int64_t* __restrict__ sizes, double* __restrict__ lam) {
+                                                       int64_t* __restrict__ sizes, double* __restrict__ lam,
+                                                       int32_t* __restrict__ paired) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
     if (!is_leader[i]) continue;
     const int64_t c = cls_of_node[i];
     sizes[c] = cnt[i];
-    lam[c] = closed_flag[i] ? -1.0 / static_cast<double>(row_ptr[i + 1] - row_ptr[i]) : 0.0;
+    const int k = kind[i];
+    lam[c] = k == 1 ? -1.0 / static_cast<double>(row_ptr[i + 1] - row_ptr[i]) : (k == 2 ? sqrt(0.5) : 0.0);
+    paired[c] = k == 2 ? 1 : 0;
   }
 }
 
@@ -248,6 +309,28 @@ nd_status twin_pass(const nd_graph* g, uint64_t seed, bool closed, hipStream_t s
   return ND_OK;
 }
 
+// Chain pass: lab[i] = leader of i's chain class (the smallest B of the group
+// for B's, the smallest A for A's) or -1.
+nd_status chain_pass(const nd_graph* g, hipStream_t st, Tmp& t, int32_t* lab) {
+  const int64_t n = g->n;
+  const int grid = grid_for(n, kBlock);
+  uint64_t *key, *key2;
+  uint32_t *val, *val2;
+  ND_CHECK(t.get(&key, n));
+  ND_CHECK(t.get(&key2, n));
+  ND_CHECK(t.get(&val, n));
+  ND_CHECK(t.get(&val2, n));
+  ND_HIP(hipMemsetAsync(lab, 0xFF, static_cast<size_t>(n) * 4, st));
+  hipLaunchKernelGGL(k_chain_keys, dim3(grid), dim3(kBlock), 0, st, g->row_ptr, g->col, n, key, val);
+  ND_LAUNCH_CHECK();
+  int nbits = 0;
+  while ((uint64_t(1) << nbits) <= static_cast<uint64_t>(n)) ++nbits;
+  ND_CHECK(radix_sort_u64(key, key2, val, val2, n, nbits, st));
+  hipLaunchKernelGGL(k_chain_groups, dim3(grid), dim3(kBlock), 0, st, key, val, n, g->row_ptr, g->col, lab);
+  ND_LAUNCH_CHECK();
+  return ND_OK;
+}
+
 nd_status twins_impl(const nd_graph* g, uint64_t seed, uint32_t kinds, hipStream_t st, nd_motifs* out) {
   const int64_t n = g->n;
   out->n = n;
@@ -259,26 +342,25 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, uint32_t kinds, hipStream
   }
   Tmp t;
   const int grid = grid_for(n, kBlock);
-  int32_t *lab, *closed_flag;
+  // per node: leader of its class (-1 outside the classes) and kind
+  // (0 open twins, 1 closed twins, 2 chains)
+  int32_t *lab, *kind, *lab2;
   ND_CHECK(t.get(&lab, n));
-  ND_CHECK(t.get(&closed_flag, n));
-  ND_HIP(hipMemsetAsync(closed_flag, 0, static_cast<size_t>(n) * 4, st));
-  if (kinds & ND_TWINS_OPEN) {
+  ND_CHECK(t.get(&kind, n));
+  ND_CHECK(t.get(&lab2, n));
+  ND_HIP(hipMemsetAsync(kind, 0, static_cast<size_t>(n) * 4, st));
+  if (kinds & ND_TWINS_OPEN)
     ND_CHECK(twin_pass(g, seed, false, st, t, lab));
-    if (kinds & ND_TWINS_CLOSED) {
-      int32_t* lab2;
-      ND_CHECK(t.get(&lab2, n));
-      ND_CHECK(twin_pass(g, seed, true, st, t, lab2));
-      hipLaunchKernelGGL(k_merge_labels, dim3(grid), dim3(kBlock), 0, st, lab, lab2, n, closed_flag);
-      ND_LAUNCH_CHECK();
-    }
-  } else {
-    // closed only: every labelled node is a closed twin
-    int32_t* lab0;
-    ND_CHECK(t.get(&lab0, n));
+  else
     ND_HIP(hipMemsetAsync(lab, 0xFF, static_cast<size_t>(n) * 4, st));
-    ND_CHECK(twin_pass(g, seed, true, st, t, lab0));
-    hipLaunchKernelGGL(k_merge_labels, dim3(grid), dim3(kBlock), 0, st, lab, lab0, n, closed_flag);
+  if (kinds & ND_TWINS_CLOSED) {
+    ND_CHECK(twin_pass(g, seed, true, st, t, lab2));
+    hipLaunchKernelGGL(k_merge_labels, dim3(grid), dim3(kBlock), 0, st, lab, lab2, n, 1, kind);
+    ND_LAUNCH_CHECK();
+  }
+  if (kinds & ND_CHAINS) {
+    ND_CHECK(chain_pass(g, st, t, lab2));
+    hipLaunchKernelGGL(k_merge_labels, dim3(grid), dim3(kBlock), 0, st, lab, lab2, n, 2, kind);
     ND_LAUNCH_CHECK();
   }
   int32_t *is_leader, *cnt;
@@ -304,8 +386,9 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, uint32_t kinds, hipStream
   int64_t* sizes;
   ND_CHECK(t.get(&sizes, n_cls));
   ND_CHECK(dalloc_t(&out->class_lambda, static_cast<size_t>(n_cls)));
-  hipLaunchKernelGGL(k_class_info, dim3(grid), dim3(kBlock), 0, st, is_leader, cnt, cls_of_node, closed_flag,
-                     g->row_ptr, n, sizes, out->class_lambda);
+  ND_CHECK(dalloc_t(&out->class_paired, static_cast<size_t>(n_cls)));
+  hipLaunchKernelGGL(k_class_info, dim3(grid), dim3(kBlock), 0, st, is_leader, cnt, cls_of_node, kind, g->row_ptr, n,
+                     sizes, out->class_lambda, out->class_paired);
   ND_LAUNCH_CHECK();
   ND_CHECK(exclusive_scan_i64(sizes, out->class_ptr, n_cls, tot, st));
   ND_HIP(hipMemcpyAsync(out->class_ptr + n_cls, tot, 8, hipMemcpyDeviceToDevice, st));
@@ -314,15 +397,27 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, uint32_t kinds, hipStream
   // spikes: total (|C| - 1) per distinct eigenvalue, ascending
   std::vector<int64_t> h_sizes(static_cast<size_t>(n_cls));
   std::vector<double> h_lam(static_cast<size_t>(n_cls));
+  std::vector<int32_t> h_pair(static_cast<size_t>(n_cls));
+  ND_HIP(hipMemcpyAsync(h_pair.data(), out->class_paired, static_cast<size_t>(n_cls) * 4, hipMemcpyDeviceToHost, st));
   ND_HIP(hipMemcpyAsync(h_sizes.data(), sizes, static_cast<size_t>(n_cls) * 8, hipMemcpyDeviceToHost, st));
   ND_HIP(hipMemcpyAsync(h_lam.data(), out->class_lambda, static_cast<size_t>(n_cls) * 8, hipMemcpyDeviceToHost, st));
   ND_HIP(hipStreamSynchronize(st));
   out->n_members = n_mem;
-  std::map<double, int64_t> acc;
-  for (int64_t c = 0; c < n_cls; ++c) acc[h_lam[c]] += h_sizes[c] - 1;
+  // removed dimensions per distinct eigenvalue (multiples of 1/2: exact in
+  // any order); a chain class holds half of its dimensions at each of +-h
+  std::map<double, double> acc;
+  for (int64_t c = 0; c < n_cls; ++c) {
+    const double dims = static_cast<double>(h_sizes[c] - 1);
+    if (h_pair[c]) {
+      acc[h_lam[c]] += 0.5 * dims;
+      acc[-h_lam[c]] += 0.5 * dims;
+    } else {
+      acc[h_lam[c]] += dims;
+    }
+  }
   for (const auto& kv : acc) {
     out->spike_lambda.push_back(kv.first);
-    out->spike_weight.push_back(static_cast<double>(kv.second) / static_cast<double>(n));
+    out->spike_weight.push_back(kv.second / static_cast<double>(n));
   }
   const size_t ns = out->spike_lambda.size();
   ND_CHECK(dalloc_t(&out->spikes_d, 2 * ns));
@@ -353,6 +448,7 @@ nd_motifs::~nd_motifs() {
   nd::dfree(class_ptr);
   nd::dfree(members);
   nd::dfree(class_lambda);
+  nd::dfree(class_paired);
   nd::dfree(spikes_d);
 }
 
@@ -363,8 +459,8 @@ nd_status nd_motif_filter(const nd_graph* g, uint64_t seed, uint32_t kinds, void
   ND_REQUIRE(out != nullptr, "nd_motif_filter: out is NULL");
   *out = nullptr;
   ND_REQUIRE(g != nullptr, "nd_motif_filter: graph is NULL");
-  if (kinds == 0 || (kinds & ~(ND_TWINS_OPEN | ND_TWINS_CLOSED)) != 0) {
-    nd::set_error("nd_motif_filter: kinds=0x%x; implemented: ND_TWINS_OPEN, ND_TWINS_CLOSED", kinds);
+  if (kinds == 0 || (kinds & ~(ND_TWINS_OPEN | ND_TWINS_CLOSED | ND_CHAINS)) != 0) {
+    nd::set_error("nd_motif_filter: kinds=0x%x; implemented: ND_TWINS_OPEN, ND_TWINS_CLOSED, ND_CHAINS", kinds);
     return ND_EUNSUPPORTED;
   }
   std::unique_ptr<nd_motifs> m(new nd_motifs());
@@ -400,12 +496,14 @@ nd_status nd_motif_export(const nd_motifs* m, int64_t* class_ptr, int32_t* membe
   return ND_OK;
 }
 
-nd_status nd_motif_export_lambda(const nd_motifs* m, double* class_lambda) {
+nd_status nd_motif_export_lambda(const nd_motifs* m, double* class_lambda, int32_t* class_paired) {
   nd::clear_error();
-  ND_REQUIRE(m != nullptr && class_lambda != nullptr, "nd_motif_export_lambda: NULL argument");
+  ND_REQUIRE(m != nullptr, "nd_motif_export_lambda: motifs is NULL");
   ND_HIP(hipDeviceSynchronize());
-  if (m->n_classes)
+  if (m->n_classes && class_lambda)
     ND_HIP(hipMemcpy(class_lambda, m->class_lambda, static_cast<size_t>(m->n_classes) * 8, hipMemcpyDeviceToHost));
+  if (m->n_classes && class_paired)
+    ND_HIP(hipMemcpy(class_paired, m->class_paired, static_cast<size_t>(m->n_classes) * 4, hipMemcpyDeviceToHost));
   return ND_OK;
 }
 

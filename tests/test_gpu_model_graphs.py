@@ -86,16 +86,17 @@ def test_model_graph(model, nd):
 
 
 def test_motif_filtering_sharpens_the_density(nd):
-    """BA m = 1 at M = 100: removing the twin spikes (open and closed) and
-    adding them back as exact point masses brings the 99-bin density several
-    times closer to the exact histogram than the unfiltered estimate."""
+    """BA m = 1 at M = 100: removing the motif spikes (open and closed twins at
+    0, pendant chains at +-1/sqrt(2)) and adding them back as exact point
+    masses brings the 99-bin density several times closer to the exact
+    histogram than the unfiltered estimate."""
     import torch
     n, s, d = sg.barabasi_albert(5000, 1, seed=1)
     g_or = og.build_csr(n, s, d)
     lam = np.linalg.eigvalsh(og.normalized_adjacency(g_or).toarray())
     hx = rc.exact_histogram(lam, BINS)
     g = nd.nd_build_csr(n, s, d)
-    m = nd.nd_motif_filter(g, 1, 0x3)
+    m = nd.nd_motif_filter(g, 1, 0x7)
     k, M = 64, 100
     out = {}
     for label, motifs in (("plain", None), ("filtered", m)):

@@ -110,19 +110,26 @@ TWIN_GRAPHS = {
     "friendship": lambda: sg.friendship(40),
     "complete": lambda: sg.complete(9),
     "rmat10": lambda: sg.rmat(10, 4, seed=2),
+    "ba_m1": lambda: sg.barabasi_albert(3000, 1, seed=4),   # a tree: many pendant chains
 }
-KINDS = {"open": 0x1, "closed": 0x2, "both": 0x3}
+KINDS = {"open": 0x1, "closed": 0x2, "both": 0x3, "chains": 0x4, "all": 0x7}
+ORACLE_KINDS = {"open": {"open"}, "closed": {"closed"}, "both": {"open", "closed"}, "chains": {"chains"},
+                "all": {"open", "closed", "chains"}}
 
 
 def _check_classes(nd, m, g_or, kind):
     ptr, mem = nd.nd_motif_export(m)
-    cls = twins.twin_classes(g_or, kind)
+    cls, sig = twins.motif_classes(g_or, ORACLE_KINDS[kind])
     p2, m2 = twins.classes_to_arrays(cls)
     assert np.array_equal(ptr, p2) and np.array_equal(mem, m2)
-    lam = [twins.class_eigenvalue(g_or, c) for c in cls]
-    assert nd.nd_motif_export_lambda(m).tolist() == lam
-    assert m.spikes == twins.spikes(cls, lam, g_or.n)
-    return cls, lam
+    lam, paired = nd.nd_motif_export_lambda(m, paired=True)
+    for l, p, sg_ in zip(lam.tolist(), paired.tolist(), sig):
+        if p:
+            assert twins.signature(sg_) == [(l, 0.5), (-l, 0.5)]
+        else:
+            assert twins.signature(sg_) == [(l, 1.0)]
+    assert m.spikes == twins.spikes(cls, sig, g_or.n)
+    return cls, sig
 
 
 @pytest.mark.parametrize("gname", sorted(TWIN_GRAPHS))
@@ -132,9 +139,11 @@ def test_twin_kinds_bit_exact(nd, gname, kind):
     g_or = og.build_csr(n, s, d)
     g = nd.nd_build_csr(n, s, d)
     m = nd.nd_motif_filter(g, 7, KINDS[kind])
-    cls, lam = _check_classes(nd, m, g_or, kind)
+    cls, sig = _check_classes(nd, m, g_or, kind)
     if gname == "mixed" and kind == "both":
-        assert 0.0 in lam and -0.5 in lam and -1.0 / 3.0 in lam and -0.25 in lam
+        assert 0.0 in sig and -0.5 in sig and -1.0 / 3.0 in sig and -0.25 in sig
+    if gname == "ba_m1" and kind in ("chains", "all"):
+        assert any(isinstance(x, list) for x in sig)
 
 
 def test_twins_under_forced_hash_collisions(nd, monkeypatch):
@@ -144,21 +153,22 @@ def test_twins_under_forced_hash_collisions(nd, monkeypatch):
     g_or = og.build_csr(n, s, d)
     g = nd.nd_build_csr(n, s, d)
     monkeypatch.setenv("ND_TWIN_HASH_BITS", "3")
-    for kind in ("open", "closed", "both"):
+    for kind in ("open", "closed", "both", "all"):
         m = nd.nd_motif_filter(g, 11, KINDS[kind])
         _check_classes(nd, m, g_or, kind)
 
 
-def test_filtered_moments_both_kinds(nd):
-    """Probes projected over open and closed classes; per-node rows get back
-    (1 - 1/|C|) T_m(lambda_C) and mu the spikes sum_s w_s T_m(lambda_s)."""
+@pytest.mark.parametrize("gname", ["mixed", "ba_m1"])
+def test_filtered_moments_all_kinds(nd, gname):
+    """Probes projected over open, closed and chain classes; per-node rows get
+    back (1 - 1/|C|) times the class's share of T_m at its eigenvalues and mu
+    the spikes sum_s w_s T_m(lambda_s)."""
     import torch
-    n, s, d = _mixed_twins()
+    n, s, d = TWIN_GRAPHS[gname]()
     g_or = og.build_csr(n, s, d)
     g = nd.nd_build_csr(n, s, d)
-    m = nd.nd_motif_filter(g, 5, KINDS["both"])
-    cls = twins.twin_classes(g_or, "both")
-    lam = [twins.class_eigenvalue(g_or, c) for c in cls]
+    m = nd.nd_motif_filter(g, 5, KINDS["all"])
+    cls, lam = twins.motif_classes(g_or, ORACLE_KINDS["all"])
     k, M = 24, 90
     H = og.normalized_adjacency(g_or)
     Z = orng.rademacher(g_or.n, k, 31)
@@ -415,7 +425,7 @@ def test_errors(nd):
         nd.nd_build_csr(3, np.array([0, 1], np.int32), np.array([1, 5], np.int32))
     assert e.value.status == nd.ND_EINVAL
     g = nd.nd_build_csr(4, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
-    for bad in (0x4, 0x0, 0x5):
+    for bad in (0x8, 0x0, 0x9):
         with pytest.raises(nd.NDError) as e:
             nd.nd_motif_filter(g, 1, kinds=bad)
         assert e.value.status == nd.ND_EUNSUPPORTED
