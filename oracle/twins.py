@@ -17,14 +17,18 @@ C of such nodes contributes |C| - 1 eigenvalues at -1/d (the spikes at -1/2,
 -1/3, ... of the paper's spectra).  A node cannot have twins of both kinds
 (an open twin j and a closed twin k would force k ~ j, hence j in N[i]).
 
-Pendant chains (the figure's panel at +-1/sqrt(2)): c >= 2 paths E - B - A
-hanging off the same node E (deg B = 2, deg A = 1).  On the differences
-between copies H couples each A to its B with 1/sqrt(2), so the
-2(c - 1)-dimensional space of differences carries c - 1 eigenvalues at
-+1/sqrt(2) and c - 1 at -1/sqrt(2).  They are handled as two classes (the
+Pendant twins (the figure's panels at +-1/sqrt(2) and, on the right, +-1/2):
+c >= 2 nodes B of degree d >= 2 that each carry one private leaf A (and no
+other leaf) and have the same remaining neighbourhood N(B) - {A}.  On the
+differences between copies H couples each A to its B with h = 1/sqrt(d) and
+the shared neighbours cancel, so the 2(c - 1)-dimensional space of
+differences carries c - 1 eigenvalues at +h and c - 1 at -h (d = 2: pendant
+chains E - B - A on one node E, +-1/sqrt(2); d = 4: a pendant edge on nodes
+joined to the same three hubs, +-1/2).  They are handled as two classes (the
 A's and the B's) whose projection is again the class mean; each class holds
 half of the pair, written as the signature [(+h, 1/2), (-h, 1/2)], and the
 diagonal of T_m(H) on the removed space is (1 - 1/c)(T_m(h) + T_m(-h))/2.
+Pendant-twin nodes are never twins of either kind.
 
 The paper detects them with a random hash w = Hz (equal w_i = w_j with high
 probability means equal neighbourhoods); here the oracle groups nodes by the
@@ -88,37 +92,39 @@ def signature(sig):
     return [(float(l), float(f)) for l, f in sig]
 
 
-def chain_classes(g) -> list:
-    """Pendant chains grouped by their attachment node: pairs (B-class,
-    A-class), members ascending, for every node E with >= 2 paths E - B - A
-    (deg B = 2, deg A = 1, B's other neighbour E not a leaf)."""
+def pendant_classes(g) -> list:
+    """Pendant twins: triples (B-class, A-class, d), members ascending, for
+    every group of >= 2 nodes B (degree d >= 2, exactly one leaf neighbour A)
+    with equal N(B) - {A}."""
     deg = np.diff(g.row_ptr)
     groups = {}
     for b in range(g.n):
-        if deg[b] != 2:
+        if deg[b] < 2:
             continue
-        u, v = (int(x) for x in g.neighbors(b))
-        if (deg[u] == 1) == (deg[v] == 1):
+        nb = g.neighbors(b).tolist()
+        leaves = [x for x in nb if deg[x] == 1]
+        if len(leaves) != 1:
             continue
-        a, e = (u, v) if deg[u] == 1 else (v, u)
-        groups.setdefault(e, []).append((b, a))
+        rest = tuple(x for x in nb if x != leaves[0])
+        groups.setdefault(rest, []).append((b, leaves[0]))
     out = []
-    for e in sorted(groups):
-        if len(groups[e]) >= 2:
-            out.append((sorted(b for b, _ in groups[e]), sorted(a for _, a in groups[e])))
+    for rest, v in groups.items():
+        if len(v) >= 2:
+            out.append((sorted(b for b, _ in v), sorted(a for _, a in v), len(rest) + 1))
+    out.sort(key=lambda t: min(t[0][0], t[1][0]))
     return out
 
 
 def motif_classes(g, kinds) -> tuple:
-    """All classes of the requested kinds ("open", "closed", "chains"), in
+    """All classes of the requested kinds ("open", "closed", "pendants"), in
     canonical order (by smallest member), with their signatures."""
     cls = []
     for kind in ("open", "closed"):
         if kind in kinds:
             cls += [(c, class_eigenvalue(g, c)) for c in twin_classes(g, kind)]
-    if "chains" in kinds:
-        h = float(np.sqrt(0.5))   # 1/sqrt(2), correctly rounded
-        for cb, ca in chain_classes(g):
+    if "pendants" in kinds:
+        for cb, ca, d in pendant_classes(g):
+            h = float(np.sqrt(1.0 / d))   # 1/sqrt(d), correctly rounded
             cls += [(cb, [(h, 0.5), (-h, 0.5)]), (ca, [(h, 0.5), (-h, 0.5)])]
     cls.sort(key=lambda t: t[0][0])
     return [c for c, _ in cls], [sgn for _, sgn in cls]

@@ -328,21 +328,30 @@ def test_paper_motif_figure_spikes():
         assert [5, 6] in cls and twins.class_eigenvalue(g, [5, 6]) == lam
 
 
-# ------------------------------------------------------------ pendant chains
-def brute_chains(g):
+# ------------------------------------------------------------ pendant twins
+def brute_pendants(g):
     deg = np.diff(g.row_ptr)
-    by_e = {}
+    cand = {}
     for b in range(g.n):
-        nb = g.neighbors(b).tolist()
+        nb = set(g.neighbors(b).tolist())
         leaves = [x for x in nb if deg[x] == 1]
-        if deg[b] == 2 and len(leaves) == 1:
-            e = [x for x in nb if x != leaves[0]][0]
-            by_e.setdefault(e, []).append((b, leaves[0]))
-    return {e: v for e, v in by_e.items() if len(v) >= 2}
+        if deg[b] >= 2 and len(leaves) == 1:
+            cand[b] = (leaves[0], frozenset(nb - {leaves[0]}))
+    groups = []
+    seen = set()
+    for b in sorted(cand):
+        if b in seen:
+            continue
+        grp = [c for c in sorted(cand) if cand[c][1] == cand[b][1]]
+        seen.update(grp)
+        if len(grp) >= 2:
+            groups.append((grp, sorted(cand[c][0] for c in grp)))
+    return groups
 
 
-def _chain_graph(seed):
-    # ER core plus groups of 2..4 pendant paths on random core nodes
+def _pendant_graph(seed):
+    # ER core plus groups of 2..4 pendant paths on single core nodes (d = 2)
+    # and groups of nodes with a private leaf joined to the same 3 hubs (d = 4)
     n0, s, d = sg.erdos_renyi(80, 0.06, seed=seed)
     rng = np.random.default_rng(seed)
     ss, dd, nxt = list(s), list(d), n0
@@ -351,30 +360,40 @@ def _chain_graph(seed):
             ss += [int(e), nxt]
             dd += [nxt, nxt + 1]
             nxt += 2
+    for _ in range(2):
+        hubs = rng.choice(n0, 3, replace=False)
+        for _ in range(int(rng.integers(2, 4))):
+            ss += [nxt] * 3 + [nxt]
+            dd += [int(h) for h in hubs] + [nxt + 1]
+            nxt += 2
     return nxt, np.array(ss, np.int32), np.array(dd, np.int32)
 
 
-@pytest.mark.parametrize("gen", [_chain_graph(1), _chain_graph(2), sg.barabasi_albert(400, 1, seed=3)])
-def test_chain_classes_match_bruteforce(gen):
+@pytest.mark.parametrize("gen", [_pendant_graph(1), _pendant_graph(2), sg.barabasi_albert(400, 1, seed=3)])
+def test_pendant_classes_match_bruteforce(gen):
     g, _ = graph_of(gen)
-    got = twins.chain_classes(g)
-    want = brute_chains(g)
-    assert len(got) == len(want)
-    for cb, ca in got:
-        e = int(g.neighbors(cb[0])[np.diff(g.row_ptr)[g.neighbors(cb[0])] != 1][0])
-        assert sorted(b for b, _ in want[e]) == cb and sorted(a for _, a in want[e]) == ca
+    got = sorted((cb, ca) for cb, ca, _ in twins.pendant_classes(g))
+    assert got == sorted((cb, ca) for cb, ca in brute_pendants(g))
+    deg = np.diff(g.row_ptr)
+    for cb, ca, d in twins.pendant_classes(g):
+        assert all(deg[b] == d for b in cb)
+    # disjoint from the twin classes
+    tw = set(x for k in twins.twin_classes(g, "both") for x in k)
+    assert not (tw & set(x for cb, ca, _ in twins.pendant_classes(g) for x in cb + ca))
 
 
-def test_chain_spectrum_and_projection():
-    """Each group of c chains removes c-1 eigenvalues at +1/sqrt(2) and c-1 at
-    -1/sqrt(2); what is left is the spectrum of P^T H P."""
-    g, H = graph_of(_chain_graph(3))
-    cls, sig = twins.motif_classes(g, {"open", "closed", "chains"})
+def test_pendant_spectrum_and_projection():
+    """Each group of c pendant twins of degree d removes c-1 eigenvalues at
+    +1/sqrt(d) and c-1 at -1/sqrt(d); what is left is the spectrum of P^T H P."""
+    g, H = graph_of(_pendant_graph(3))
+    cls, sig = twins.motif_classes(g, {"open", "closed", "pendants"})
     Hd = H.toarray()
     lam_h = list(np.sort(np.linalg.eigvalsh(Hd)))
-    lam_r = np.sort(np.linalg.eigvalsh(twins.basis_dense(cls, g.n).T @ Hd @ twins.basis_dense(cls, g.n)))
+    P = twins.basis_dense(cls, g.n)
+    lam_r = np.sort(np.linalg.eigvalsh(P.T @ Hd @ P))
     sp = twins.spikes(cls, sig, g.n)
-    assert any(abs(l - 2 ** -0.5) < 1e-15 for l, _ in sp) and any(abs(l + 2 ** -0.5) < 1e-15 for l, _ in sp)
+    for x in (2 ** -0.5, -(2 ** -0.5), 0.5, -0.5):
+        assert any(abs(l - x) < 1e-15 for l, _ in sp)
     for lam, w in sp:
         for _ in range(int(round(w * g.n))):
             k = int(np.argmin(np.abs(np.array(lam_h) - lam)))
@@ -383,12 +402,12 @@ def test_chain_spectrum_and_projection():
     assert np.allclose(np.sort(lam_h), lam_r, atol=1e-10)
 
 
-def test_chain_filtered_estimates_unbiased_by_enumeration():
+def test_pendant_filtered_estimates_unbiased_by_enumeration():
     # a hub with three pendant chains and a triangle: 11 nodes, all 2^11 sign vectors
     s = np.array([0, 1, 0, 3, 0, 5, 0, 7, 8, 7, 0], np.int32)
     d = np.array([1, 2, 3, 4, 5, 6, 7, 8, 9, 9, 10], np.int32)
     g, H = graph_of((11, s, d))
-    cls, sig = twins.motif_classes(g, {"open", "closed", "chains"})
+    cls, sig = twins.motif_classes(g, {"open", "closed", "pendants"})
     assert [1, 3, 5] in cls and [2, 4, 6] in cls
     Z = np.array(list(itertools.product([-1.0, 1.0], repeat=g.n))).T
     M = 9
@@ -398,16 +417,18 @@ def test_chain_filtered_estimates_unbiased_by_enumeration():
     assert np.allclose(C, l_x, atol=1e-12)
 
 
-def test_paper_figure_pendant_paths_are_chains():
-    # the figure's panel at +-1/sqrt(2): two pendant paths on one node
-    path = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "motif_spikes.txt")
-    mo = [m for m in _read_motifs(path) if m["name"] == "two_pendant_paths"][0]
+@pytest.mark.parametrize("name,cb", [("two_pendant_paths", [6, 7]), ("pendant_pair_on_three_hubs", [6, 7])])
+def test_paper_figure_pendant_panels(name, cb):
+    """The figure's panels at +-1/sqrt(2) and (right) +-1/2 are pendant twins."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "motif_spikes.txt")
+    mo = [m for m in _read_motifs(path) if m["name"] == name][0]
     _, hs, hd = sg.complete(5)
     s = np.concatenate([hs, np.array([e[0] for e in mo["edges"]], np.int32)])
     d = np.concatenate([hd, np.array([e[1] for e in mo["edges"]], np.int32)])
     g, _ = graph_of((9, s, d))
-    cls, sig = twins.motif_classes(g, {"chains"})
-    assert cls == [[5, 8], [6, 7]]
+    cls, sig = twins.motif_classes(g, {"pendants"})
+    assert cb in cls and len(cls) == 2
     sp = twins.spikes(cls, sig, g.n)
-    assert [l for l, _ in sp] == pytest.approx([-mo["lambda"][0], mo["lambda"][0]], abs=1e-15)
+    assert [l for l, _ in sp] == pytest.approx(sorted(mo["lambda"]), abs=1e-15)
     assert [w for _, w in sp] == [1 / 9, 1 / 9]
