@@ -75,8 +75,8 @@ typedef struct nd_motifs nd_motifs; /* twin classes found in a graph */
 #define ND_TWINS_OPEN 0x1u        /* nd_motif_filter: nodes with equal open neighbourhoods */
 #define ND_TWINS_CLOSED 0x2u      /* nd_motif_filter: adjacent nodes with equal closed
                                      neighbourhoods N(i) + {i} */
-#define ND_CHAINS 0x4u            /* nd_motif_filter: >= 2 pendant paths E - B - A on one
-                                     node E (deg B = 2, deg A = 1) */
+#define ND_PENDANTS 0x4u          /* nd_motif_filter: pendant twins, nodes with one private
+                                     leaf and equal remaining neighbourhoods */
 
 #define ND_KERNEL_NONE 0u         /* nd_reconstruct: plain truncated series */
 #define ND_KERNEL_JACKSON 1u      /* nd_reconstruct: Jackson damping factors */
@@ -130,17 +130,20 @@ void nd_graph_free(nd_graph* g);
  * eigenvectors e_i - e_j with eigenvalue -1/d (the blade motif at -1/2 and
  * the -1/m family: an edge attached through the same m-1 nodes).  A node
  * cannot have twins of both kinds, so the classes never overlap.
- * Pendant chains (ND_CHAINS; the figure's panel at +-1/sqrt(2)): c >= 2
- * paths E - B - A hanging off one node E (deg B = 2, deg A = 1) give two
- * classes, the B's and the A's, whose differences carry c-1 eigenvalues at
- * +1/sqrt(2) and c-1 at -1/sqrt(2); chain nodes are never twins.
+ * Pendant twins (ND_PENDANTS; the figure's panels at +-1/sqrt(2) and, on the
+ * right, +-1/2): c >= 2 nodes B of degree d >= 2 that each carry exactly one
+ * leaf A and share the rest of their neighbourhood give two classes, the B's
+ * and the A's, whose differences carry c-1 eigenvalues at +1/sqrt(d) and c-1
+ * at -1/sqrt(d) (d = 2: pendant paths E - B - A on one node E).  Candidates
+ * are grouped by the same hash-and-verify scheme on N(B) minus the leaf.
+ * Pendant-twin nodes are never twins.
  * Candidates come from a random hash of each neighbourhood,
  * h_i = sum_{j in N(i)} r_j (+ r_i for closed neighbourhoods) over Z/2^64 with
  * seeded random r (the paper hashes with w = Hz); every candidate class is
  * then confirmed by exact comparison of sorted neighbour lists, so the
  * partition does not depend on the seed.
  *   kinds  any non-empty combination of ND_TWINS_OPEN, ND_TWINS_CLOSED,
- *          ND_CHAINS.
+ *          ND_PENDANTS.
  * Output classes (size >= 2) are in canonical order: by smallest member,
  * members ascending.  Synchronises `stream`.
  * Errors: ND_EINVAL, ND_EUNSUPPORTED (other kinds), ND_ENOMEM, ND_EDEVICE. */
@@ -148,8 +151,8 @@ nd_status nd_motif_filter(const nd_graph* g, uint64_t seed, uint32_t kinds, void
                           nd_motifs** out);
 
 /* Counts and spikes (host outputs; any may be NULL).  A twin class C removes
- * |C|-1 eigenvalues at lambda_C (0 or -1/d); a chain class removes (|C|-1)/2
- * at each of +-1/sqrt(2).  The spikes are the distinct removed eigenvalues
+ * |C|-1 eigenvalues at lambda_C (0 or -1/d); a pendant-twin class removes
+ * (|C|-1)/2 at each of +-1/sqrt(d).  The spikes are the distinct removed eigenvalues
  * in ascending order, each with its removed count over N (a fraction of the
  * DOS mass).  spike_lambda/spike_weight need room
  * for *n_spikes entries: call once with them NULL to learn the count. */
@@ -161,9 +164,10 @@ nd_status nd_motif_export(const nd_motifs* m, int64_t* class_ptr, int32_t* membe
 
 /* Host copies (either may be NULL) of each class's removed eigenvalue,
  * class_lambda double [n_classes]: 0 for open twins, -1/d for closed twins of
- * degree d, 1/sqrt(2) for chain classes; and class_paired int32 [n_classes]:
- * 1 for chain classes (half of the class's removed dimensions at
- * +class_lambda, half at -class_lambda), else 0. */
+ * degree d, 1/sqrt(d) for pendant-twin classes (B's of degree d); and
+ * class_paired int32 [n_classes]: 1 for pendant-twin classes (half of the
+ * class's removed dimensions at +class_lambda, half at -class_lambda),
+ * else 0. */
 nd_status nd_motif_export_lambda(const nd_motifs* m, double* class_lambda, int32_t* class_paired);
 
 void nd_motifs_free(nd_motifs* m);
@@ -220,7 +224,7 @@ nd_status nd_cheb_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
  *   motifs   NULL, or twin classes: probes projected as in nd_cheb_moments,
  *            and each class member i gets the removed part back exactly,
  *            ldos[i][m] += (1 - 1/|C|) T_m(lambda_C) (the mean of T_m(+-lambda_C)
- *            for chain classes), so rows stay unbiased
+ *            for pendant-twin classes), so rows stay unbiased
  *            (mu then includes sum_s w_s T_m(lambda_s) over the spikes).
  *   ldos     device double [N][n_moments]
  *   ldos_sq  NULL, or device double [N][n_moments]: (1/k) sum_j v_ijm^2,

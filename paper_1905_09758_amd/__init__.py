@@ -26,7 +26,7 @@ ND_PROBE_RADEMACHER, ND_PROBE_GAUSSIAN, ND_STATE_FP64, ND_TIME_STEPS = 0x0, 0x1,
 ND_MOMENT_DOUBLING = 0x8
 ND_TWINS_OPEN = 0x1
 ND_TWINS_CLOSED = 0x2
-ND_CHAINS = 0x4
+ND_PENDANTS = 0x4
 ND_KERNEL_NONE, ND_KERNEL_JACKSON, ND_SPIKES_IN_MOMENTS = 0, 1, 0x10
 
 _STATUS = {ND_EINVAL: "ND_EINVAL", ND_ENOMEM: "ND_ENOMEM", ND_EDEVICE: "ND_EDEVICE",
@@ -250,8 +250,8 @@ def nd_motif_export(m: Motifs):
 
 def nd_motif_export_lambda(m: Motifs, paired: bool = False):
     """Eigenvalue removed by each class: 0 (open twins), -1/d (closed twins)
-    or 1/sqrt(2) (chain classes); with paired=True also the int32 flags of
-    the classes that hold +-lambda."""
+    or 1/sqrt(d) (pendant-twin classes); with paired=True also the int32
+    flags of the classes that hold +-lambda."""
     lam = np.empty(max(m.n_classes, 1), np.float64)
     pr = np.empty(max(m.n_classes, 1), np.int32)
     _check(_lib.nd_motif_export_lambda(m.handle, lam.ctypes.data, pr.ctypes.data), "nd_motif_export_lambda")

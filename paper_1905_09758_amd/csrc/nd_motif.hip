@@ -15,11 +15,13 @@
 // independent of the seed.  A node cannot have twins of both kinds, so the
 // two passes give disjoint groups.
 //
-// Pendant chains (the motif figure's panel at +-1/sqrt(2)): nodes B of degree
-// 2 with exactly one leaf neighbour A, grouped by their other neighbour E;
-// a group of c >= 2 chains gives two classes (the B's and the A's), whose
-// differences carry c-1 eigenvalues at +1/sqrt(2) and c-1 at -1/sqrt(2).
-// Chain nodes are never twins, so all classes stay disjoint.
+// Pendant twins (the motif figure's panels at +-1/sqrt(2) and +-1/2): nodes
+// B of degree d >= 2 with exactly one leaf neighbour A and equal remaining
+// neighbourhoods N(B) - {A}, found by the same hash-sort-verify passes on
+// that remaining neighbourhood.  A group of c >= 2 gives two classes (the B's
+// and the A's) whose differences carry c-1 eigenvalues at +1/sqrt(d) and c-1
+// at -1/sqrt(d).  Pendant-twin nodes are never twins, so all classes stay
+// disjoint.
 #include <cstdlib>
 #include <map>
 #include <vector>
@@ -29,16 +31,46 @@
 namespace nd {
 namespace {
 
+// The single leaf neighbour of b if b has degree >= 2 and exactly one leaf
+// neighbour, else -1.
+__device__ inline int64_t pendant_leaf(const int64_t* row_ptr, const int32_t* col, int64_t b) {
+  if (row_ptr[b + 1] - row_ptr[b] < 2) return -1;
+  int64_t leaf = -1;
+  for (int64_t e = row_ptr[b]; e < row_ptr[b + 1]; ++e) {
+    const int32_t u = col[e];
+    if (row_ptr[u + 1] - row_ptr[u] == 1) {
+      if (leaf >= 0) return -1;
+      leaf = u;
+    }
+  }
+  return leaf;
+}
+
+// Hash modes: 0 open neighbourhood, 1 closed, 2 the neighbourhood without
+// the private leaf (pendant-twin candidates; other nodes get distinct keys
+// with the top bit set, which the verification never groups).
 __global__ __launch_bounds__(kBlock) void k_twin_hash(const int64_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ col, int64_t n, uint64_t key,
-                                                      uint64_t mask, int closed, uint64_t* __restrict__ h,
+                                                      uint64_t mask, int mode, uint64_t* __restrict__ h,
                                                       uint32_t* __restrict__ idx) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    uint64_t s = closed ? splitmix64(key, static_cast<uint64_t>(i) + 1) : 0;
+    idx[i] = static_cast<uint32_t>(i);
+    if (mode == 2) {
+      const int64_t leaf = pendant_leaf(row_ptr, col, i);
+      if (leaf < 0) {
+        h[i] = (uint64_t(1) << 63) | static_cast<uint64_t>(i);
+        continue;
+      }
+      uint64_t s = 0;
+      for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+        if (col[e] != leaf) s += splitmix64(key, static_cast<uint64_t>(col[e]) + 1);
+      h[i] = (s & mask) & ~(uint64_t(1) << 63);
+      continue;
+    }
+    uint64_t s = mode == 1 ? splitmix64(key, static_cast<uint64_t>(i) + 1) : 0;
     for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) s += splitmix64(key, static_cast<uint64_t>(col[e]) + 1);
     h[i] = s & mask;
-    idx[i] = static_cast<uint32_t>(i);
   }
 }
 
@@ -56,15 +88,29 @@ __global__ __launch_bounds__(kBlock) void k_runs(const uint64_t* __restrict__ h,
 }
 
 // Open: N(a) == N(b).  Closed: a ~ b and N(a) - {b} == N(b) - {a} (sorted
-// lists compared while skipping b in a's list and a in b's list).
+// lists compared while skipping b in a's list and a in b's list).  Pendant:
+// both are candidates and N(a) - {leaf a} == N(b) - {leaf b}.
 __device__ inline bool same_neighbourhood(const int64_t* row_ptr, const int32_t* col, int64_t a, int64_t b,
-                                          bool closed) {
+                                          int mode) {
   const int64_t a0 = row_ptr[a], a1 = row_ptr[a + 1], b0 = row_ptr[b], b1 = row_ptr[b + 1];
   if (a1 - a0 != b1 - b0) return false;
-  if (!closed) {
+  if (mode == 0) {
     for (int64_t t = 0; t < a1 - a0; ++t)
       if (col[a0 + t] != col[b0 + t]) return false;
     return true;
+  }
+  if (mode == 2) {
+    const int64_t la = pendant_leaf(row_ptr, col, a), lb = pendant_leaf(row_ptr, col, b);
+    if (la < 0 || lb < 0) return false;
+    int64_t i = a0, j = b0;
+    while (true) {
+      if (i < a1 && col[i] == la) ++i;
+      if (j < b1 && col[j] == lb) ++j;
+      if (i >= a1 || j >= b1) return i >= a1 && j >= b1;
+      if (col[i] != col[j]) return false;
+      ++i;
+      ++j;
+    }
   }
   bool adjacent = false;
   int64_t i = a0, j = b0;
@@ -89,7 +135,7 @@ __device__ inline bool same_neighbourhood(const int64_t* row_ptr, const int32_t*
 // smallest mismatching position of the group as the new group's leader.
 __global__ __launch_bounds__(kBlock) void k_verify(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                                    const uint32_t* __restrict__ node, const int64_t* __restrict__ label,
-                                                   int64_t n, int closed, int32_t* __restrict__ mism,
+                                                   int64_t n, int mode, int32_t* __restrict__ mism,
                                                    unsigned long long* __restrict__ newlab,
                                                    unsigned long long* __restrict__ n_mism) {
   unsigned long long cnt = 0;
@@ -98,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(const int64_t* __restrict__ r
     const int64_t l = label[p];
     mism[p] = 0;
     if (l == p) continue;
-    if (!same_neighbourhood(row_ptr, col, node[p], node[l], closed != 0)) {
+    if (!same_neighbourhood(row_ptr, col, node[p], node[l], mode)) {
       mism[p] = 1;
       atomicMin(&newlab[l], static_cast<unsigned long long>(p));
       cnt++;
@@ -146,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_node_labels(const int64_t* __restric
 }
 
 // Merge another pass's labels into lab (the kinds are disjoint), marking
-// the merged nodes with `kind_id` (1 closed twins, 2 pendant chains).
+// the merged nodes with `kind_id` (1 closed twins, 2 pendant twins).
 __global__ __launch_bounds__(kBlock) void k_merge_labels(int32_t* __restrict__ lab, const int32_t* __restrict__ lab2,
                                                          int64_t n, int kind_id, int32_t* __restrict__ kind) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
@@ -158,52 +204,25 @@ __global__ __launch_bounds__(kBlock) void k_merge_labels(int32_t* __restrict__ l
   }
 }
 
-// Chain candidates: key = the attachment node E of B (n when B is not a
-// chain middle), payload B.
-__global__ __launch_bounds__(kBlock) void k_chain_keys(const int64_t* __restrict__ row_ptr,
-                                                       const int32_t* __restrict__ col, int64_t n,
-                                                       uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+// Pendant twins: the A-class of a B-class is led by its smallest leaf.
+__global__ __launch_bounds__(kBlock) void k_pendant_min_leaf(const int64_t* __restrict__ row_ptr,
+                                                             const int32_t* __restrict__ col,
+                                                             const int32_t* __restrict__ lab, int64_t n,
+                                                             int32_t* __restrict__ amin) {
+  for (int64_t b = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; b < n;
+       b += static_cast<int64_t>(gridDim.x) * kBlock)
+    if (lab[b] >= 0) atomicMin(&amin[lab[b]], static_cast<int32_t>(pendant_leaf(row_ptr, col, b)));
+}
+
+__global__ __launch_bounds__(kBlock) void k_pendant_leaf_labels(const int64_t* __restrict__ row_ptr,
+                                                                const int32_t* __restrict__ col,
+                                                                int32_t* __restrict__ lab, int64_t n,
+                                                                const int32_t* __restrict__ amin) {
   for (int64_t b = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; b < n;
        b += static_cast<int64_t>(gridDim.x) * kBlock) {
-    uint64_t k = static_cast<uint64_t>(n);
-    if (row_ptr[b + 1] - row_ptr[b] == 2) {
-      const int32_t u = col[row_ptr[b]], v = col[row_ptr[b] + 1];
-      const bool lu = row_ptr[u + 1] - row_ptr[u] == 1, lv = row_ptr[v + 1] - row_ptr[v] == 1;
-      if (lu != lv) k = static_cast<uint64_t>(lu ? v : u);
-    }
-    key[b] = k;
-    val[b] = static_cast<uint32_t>(b);
-  }
-}
-
-// The leaf of chain middle b.
-__device__ inline int32_t chain_leaf(const int64_t* row_ptr, const int32_t* col, int64_t b) {
-  const int32_t u = col[row_ptr[b]];
-  return row_ptr[u + 1] - row_ptr[u] == 1 ? u : col[row_ptr[b] + 1];
-}
-
-// Runs of equal key (sorted, B ascending within a run) of length >= 2: the
-// thread at a run's head labels the B's with the run's first B and the
-// leaves with the run's smallest leaf (one pass over each run).
-__global__ __launch_bounds__(kBlock) void k_chain_groups(const uint64_t* __restrict__ key,
-                                                         const uint32_t* __restrict__ val, int64_t n,
-                                                         const int64_t* __restrict__ row_ptr,
-                                                         const int32_t* __restrict__ col, int32_t* __restrict__ lab) {
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
-       p += static_cast<int64_t>(gridDim.x) * kBlock) {
-    if (key[p] == static_cast<uint64_t>(n) || (p > 0 && key[p - 1] == key[p])) continue;
-    int64_t e = p;
-    while (e + 1 < n && key[e + 1] == key[p]) ++e;
-    if (e == p) continue;  // a single chain
-    int32_t amin = chain_leaf(row_ptr, col, val[p]);
-    for (int64_t t = p + 1; t <= e; ++t) {
-      const int32_t a = chain_leaf(row_ptr, col, val[t]);
-      amin = a < amin ? a : amin;
-    }
-    for (int64_t t = p; t <= e; ++t) {
-      lab[val[t]] = static_cast<int32_t>(val[p]);
-      lab[chain_leaf(row_ptr, col, val[t])] = amin;
-    }
+    if (row_ptr[b + 1] - row_ptr[b] < 2) continue;  // leaves are never B's
+    const int32_t l = lab[b];
+    if (l >= 0) lab[pendant_leaf(row_ptr, col, b)] = amin[l];
   }
 }
 
@@ -218,14 +237,16 @@ __global__ __launch_bounds__(kBlock) void k_leaders(const int32_t* __restrict__ 
 }
 
 // Class c (classes ordered by leader node): size, removed eigenvalue (0 for
-// open twins, -1/d for closed twins of degree d, 1/sqrt(2) for chain classes,
-// which hold the pair +-1/sqrt(2) with half of the class's dimensions each)
-// and the pair flag.
+// open twins, -1/d for closed twins of degree d, 1/sqrt(d) for pendant-twin
+// classes of degree-d B's, which hold the pair +-1/sqrt(d) with half of the
+// class's dimensions each; an A-class leader is a leaf whose neighbour is a
+// B) and the pair flag.
 __global__ __launch_bounds__(kBlock) void k_class_info(const int32_t* __restrict__ is_leader,
                                                        const int32_t* __restrict__ cnt,
                                                        const int64_t* __restrict__ cls_of_node,
                                                        const int32_t* __restrict__ kind,
-                                                       const int64_t* __restrict__ row_ptr, int64_t n,
+                                                       const int64_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col, int64_t n,
                                                        int64_t* __restrict__ sizes, double* __restrict__ lam,
                                                        int32_t* __restrict__ paired) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
@@ -234,7 +255,15 @@ __global__ __launch_bounds__(kBlock) void k_class_info(const int32_t* __restrict
     const int64_t c = cls_of_node[i];
     sizes[c] = cnt[i];
     const int k = kind[i];
-    lam[c] = k == 1 ? -1.0 / static_cast<double>(row_ptr[i + 1] - row_ptr[i]) : (k == 2 ? sqrt(0.5) : 0.0);
+    const int64_t d = row_ptr[i + 1] - row_ptr[i];
+    double l = 0.0;
+    if (k == 1) {
+      l = -1.0 / static_cast<double>(d);
+    } else if (k == 2) {
+      const int64_t db = d >= 2 ? d : row_ptr[col[row_ptr[i]] + 1] - row_ptr[col[row_ptr[i]]];
+      l = sqrt(1.0 / static_cast<double>(db));
+    }
+    lam[c] = l;
     paired[c] = k == 2 ? 1 : 0;
   }
 }
@@ -255,7 +284,8 @@ __global__ __launch_bounds__(kBlock) void k_member_keys(const int32_t* __restric
 }
 
 // One detection pass: lab[i] = leader node of i's exact group (size >= 2) or -1.
-nd_status twin_pass(const nd_graph* g, uint64_t seed, bool closed, hipStream_t st, Tmp& t, int32_t* lab) {
+// Detection pass in hash mode `mode` (0 open, 1 closed, 2 pendant twins).
+nd_status twin_pass(const nd_graph* g, uint64_t seed, int mode, hipStream_t st, Tmp& t, int32_t* lab) {
   const int64_t n = g->n;
   const int grid = grid_for(n, kBlock);
   uint64_t *h, *h2;
@@ -270,7 +300,7 @@ nd_status twin_pass(const nd_graph* g, uint64_t seed, bool closed, hipStream_t s
     if (b > 0 && b < 64) mask = (1ull << b) - 1ull;
   }
   hipLaunchKernelGGL(k_twin_hash, dim3(grid), dim3(kBlock), 0, st, g->row_ptr, g->col, n, splitmix64(seed, 1), mask,
-                     closed ? 1 : 0, h, node);
+                     mode, h, node);
   ND_LAUNCH_CHECK();
   ND_CHECK(radix_sort_u64(h, h2, node, node2, n, 64, st));
   int64_t* label;
@@ -290,7 +320,7 @@ nd_status twin_pass(const nd_graph* g, uint64_t seed, bool closed, hipStream_t s
   for (int64_t iter = 0; iter < n; ++iter) {
     ND_HIP(hipMemsetAsync(n_mism, 0, 8, st));
     hipLaunchKernelGGL(k_verify, dim3(grid), dim3(kBlock), 0, st, g->row_ptr, g->col, node, label, n,
-                       closed ? 1 : 0, mism, newlab, n_mism);
+                       mode, mism, newlab, n_mism);
     ND_LAUNCH_CHECK();
     unsigned long long hm = 0;
     ND_HIP(hipMemcpyAsync(&hm, n_mism, 8, hipMemcpyDeviceToHost, st));
@@ -309,24 +339,18 @@ nd_status twin_pass(const nd_graph* g, uint64_t seed, bool closed, hipStream_t s
   return ND_OK;
 }
 
-// Chain pass: lab[i] = leader of i's chain class (the smallest B of the group
-// for B's, the smallest A for A's) or -1.
-nd_status chain_pass(const nd_graph* g, hipStream_t st, Tmp& t, int32_t* lab) {
+// Pendant-twin pass: lab[i] = leader of i's class (the smallest B of the
+// group for B's, the smallest leaf for A's) or -1.
+nd_status pendant_pass(const nd_graph* g, uint64_t seed, hipStream_t st, Tmp& t, int32_t* lab) {
   const int64_t n = g->n;
   const int grid = grid_for(n, kBlock);
-  uint64_t *key, *key2;
-  uint32_t *val, *val2;
-  ND_CHECK(t.get(&key, n));
-  ND_CHECK(t.get(&key2, n));
-  ND_CHECK(t.get(&val, n));
-  ND_CHECK(t.get(&val2, n));
-  ND_HIP(hipMemsetAsync(lab, 0xFF, static_cast<size_t>(n) * 4, st));
-  hipLaunchKernelGGL(k_chain_keys, dim3(grid), dim3(kBlock), 0, st, g->row_ptr, g->col, n, key, val);
+  ND_CHECK(twin_pass(g, seed, 2, st, t, lab));
+  int32_t* amin;
+  ND_CHECK(t.get(&amin, n));
+  ND_HIP(hipMemsetAsync(amin, 0x7F, static_cast<size_t>(n) * 4, st));
+  hipLaunchKernelGGL(k_pendant_min_leaf, dim3(grid), dim3(kBlock), 0, st, g->row_ptr, g->col, lab, n, amin);
   ND_LAUNCH_CHECK();
-  int nbits = 0;
-  while ((uint64_t(1) << nbits) <= static_cast<uint64_t>(n)) ++nbits;
-  ND_CHECK(radix_sort_u64(key, key2, val, val2, n, nbits, st));
-  hipLaunchKernelGGL(k_chain_groups, dim3(grid), dim3(kBlock), 0, st, key, val, n, g->row_ptr, g->col, lab);
+  hipLaunchKernelGGL(k_pendant_leaf_labels, dim3(grid), dim3(kBlock), 0, st, g->row_ptr, g->col, lab, n, amin);
   ND_LAUNCH_CHECK();
   return ND_OK;
 }
@@ -343,23 +367,23 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, uint32_t kinds, hipStream
   Tmp t;
   const int grid = grid_for(n, kBlock);
   // per node: leader of its class (-1 outside the classes) and kind
-  // (0 open twins, 1 closed twins, 2 chains)
+  // (0 open twins, 1 closed twins, 2 pendant twins)
   int32_t *lab, *kind, *lab2;
   ND_CHECK(t.get(&lab, n));
   ND_CHECK(t.get(&kind, n));
   ND_CHECK(t.get(&lab2, n));
   ND_HIP(hipMemsetAsync(kind, 0, static_cast<size_t>(n) * 4, st));
   if (kinds & ND_TWINS_OPEN)
-    ND_CHECK(twin_pass(g, seed, false, st, t, lab));
+    ND_CHECK(twin_pass(g, seed, 0, st, t, lab));
   else
     ND_HIP(hipMemsetAsync(lab, 0xFF, static_cast<size_t>(n) * 4, st));
   if (kinds & ND_TWINS_CLOSED) {
-    ND_CHECK(twin_pass(g, seed, true, st, t, lab2));
+    ND_CHECK(twin_pass(g, seed, 1, st, t, lab2));
     hipLaunchKernelGGL(k_merge_labels, dim3(grid), dim3(kBlock), 0, st, lab, lab2, n, 1, kind);
     ND_LAUNCH_CHECK();
   }
-  if (kinds & ND_CHAINS) {
-    ND_CHECK(chain_pass(g, st, t, lab2));
+  if (kinds & ND_PENDANTS) {
+    ND_CHECK(pendant_pass(g, seed, st, t, lab2));
     hipLaunchKernelGGL(k_merge_labels, dim3(grid), dim3(kBlock), 0, st, lab, lab2, n, 2, kind);
     ND_LAUNCH_CHECK();
   }
@@ -387,8 +411,8 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, uint32_t kinds, hipStream
   ND_CHECK(t.get(&sizes, n_cls));
   ND_CHECK(dalloc_t(&out->class_lambda, static_cast<size_t>(n_cls)));
   ND_CHECK(dalloc_t(&out->class_paired, static_cast<size_t>(n_cls)));
-  hipLaunchKernelGGL(k_class_info, dim3(grid), dim3(kBlock), 0, st, is_leader, cnt, cls_of_node, kind, g->row_ptr, n,
-                     sizes, out->class_lambda, out->class_paired);
+  hipLaunchKernelGGL(k_class_info, dim3(grid), dim3(kBlock), 0, st, is_leader, cnt, cls_of_node, kind, g->row_ptr,
+                     g->col, n, sizes, out->class_lambda, out->class_paired);
   ND_LAUNCH_CHECK();
   ND_CHECK(exclusive_scan_i64(sizes, out->class_ptr, n_cls, tot, st));
   ND_HIP(hipMemcpyAsync(out->class_ptr + n_cls, tot, 8, hipMemcpyDeviceToDevice, st));
@@ -404,7 +428,7 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, uint32_t kinds, hipStream
   ND_HIP(hipStreamSynchronize(st));
   out->n_members = n_mem;
   // removed dimensions per distinct eigenvalue (multiples of 1/2: exact in
-  // any order); a chain class holds half of its dimensions at each of +-h
+  // any order); a pendant-twin class holds half of its dimensions at each of +-h
   std::map<double, double> acc;
   for (int64_t c = 0; c < n_cls; ++c) {
     const double dims = static_cast<double>(h_sizes[c] - 1);
@@ -459,8 +483,8 @@ nd_status nd_motif_filter(const nd_graph* g, uint64_t seed, uint32_t kinds, void
   ND_REQUIRE(out != nullptr, "nd_motif_filter: out is NULL");
   *out = nullptr;
   ND_REQUIRE(g != nullptr, "nd_motif_filter: graph is NULL");
-  if (kinds == 0 || (kinds & ~(ND_TWINS_OPEN | ND_TWINS_CLOSED | ND_CHAINS)) != 0) {
-    nd::set_error("nd_motif_filter: kinds=0x%x; implemented: ND_TWINS_OPEN, ND_TWINS_CLOSED, ND_CHAINS", kinds);
+  if (kinds == 0 || (kinds & ~(ND_TWINS_OPEN | ND_TWINS_CLOSED | ND_PENDANTS)) != 0) {
+    nd::set_error("nd_motif_filter: kinds=0x%x; implemented: ND_TWINS_OPEN, ND_TWINS_CLOSED, ND_PENDANTS", kinds);
     return ND_EUNSUPPORTED;
   }
   std::unique_ptr<nd_motifs> m(new nd_motifs());

@@ -87,7 +87,7 @@ def test_model_graph(model, nd):
 
 def test_motif_filtering_sharpens_the_density(nd):
     """BA m = 1 at M = 100: removing the motif spikes (open and closed twins at
-    0, pendant chains at +-1/sqrt(2)) and adding them back as exact point
+    0, pendant twins at +-1/sqrt(2)) and adding them back as exact point
     masses brings the 99-bin density several times closer to the exact
     histogram than the unfiltered estimate."""
     import torch

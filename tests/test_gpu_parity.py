@@ -110,11 +110,32 @@ TWIN_GRAPHS = {
     "friendship": lambda: sg.friendship(40),
     "complete": lambda: sg.complete(9),
     "rmat10": lambda: sg.rmat(10, 4, seed=2),
-    "ba_m1": lambda: sg.barabasi_albert(3000, 1, seed=4),   # a tree: many pendant chains
+    "ba_m1": lambda: sg.barabasi_albert(3000, 1, seed=4),   # a tree: many pendant twins
+    "pendants": lambda: _pendant_graph(5),
 }
-KINDS = {"open": 0x1, "closed": 0x2, "both": 0x3, "chains": 0x4, "all": 0x7}
-ORACLE_KINDS = {"open": {"open"}, "closed": {"closed"}, "both": {"open", "closed"}, "chains": {"chains"},
-                "all": {"open", "closed", "chains"}}
+
+
+def _pendant_graph(seed):
+    """ER core plus pendant paths on single core nodes (d = 2) and nodes with
+    a private leaf joined to the same three hubs (d = 4)."""
+    n0, s, d = sg.erdos_renyi(400, 0.015, seed=seed)
+    rng = np.random.default_rng(seed)
+    ss, dd, nxt = list(s), list(d), n0
+    for e in rng.choice(n0, 20, replace=False):
+        for _ in range(int(rng.integers(2, 5))):
+            ss += [int(e), nxt]
+            dd += [nxt, nxt + 1]
+            nxt += 2
+    for _ in range(10):
+        hubs = rng.choice(n0, 3, replace=False)
+        for _ in range(int(rng.integers(2, 4))):
+            ss += [nxt] * 3 + [nxt]
+            dd += [int(h) for h in hubs] + [nxt + 1]
+            nxt += 2
+    return nxt, np.array(ss, np.int32), np.array(dd, np.int32)
+KINDS = {"open": 0x1, "closed": 0x2, "both": 0x3, "pendants": 0x4, "all": 0x7}
+ORACLE_KINDS = {"open": {"open"}, "closed": {"closed"}, "both": {"open", "closed"}, "pendants": {"pendants"},
+                "all": {"open", "closed", "pendants"}}
 
 
 def _check_classes(nd, m, g_or, kind):
@@ -142,8 +163,11 @@ def test_twin_kinds_bit_exact(nd, gname, kind):
     cls, sig = _check_classes(nd, m, g_or, kind)
     if gname == "mixed" and kind == "both":
         assert 0.0 in sig and -0.5 in sig and -1.0 / 3.0 in sig and -0.25 in sig
-    if gname == "ba_m1" and kind in ("chains", "all"):
+    if gname in ("ba_m1", "pendants") and kind in ("pendants", "all"):
         assert any(isinstance(x, list) for x in sig)
+    if gname == "pendants" and kind == "all":
+        lams = {l for l, _ in m.spikes}
+        assert {0.5, -0.5} <= lams and any(abs(abs(l) - 2 ** -0.5) < 1e-15 for l in lams)
 
 
 def test_twins_under_forced_hash_collisions(nd, monkeypatch):
@@ -158,9 +182,9 @@ def test_twins_under_forced_hash_collisions(nd, monkeypatch):
         _check_classes(nd, m, g_or, kind)
 
 
-@pytest.mark.parametrize("gname", ["mixed", "ba_m1"])
+@pytest.mark.parametrize("gname", ["mixed", "ba_m1", "pendants"])
 def test_filtered_moments_all_kinds(nd, gname):
-    """Probes projected over open, closed and chain classes; per-node rows get
+    """Probes projected over open, closed and pendant-twin classes; per-node rows get
     back (1 - 1/|C|) times the class's share of T_m at its eigenvalues and mu
     the spikes sum_s w_s T_m(lambda_s)."""
     import torch
