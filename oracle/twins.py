@@ -30,6 +30,15 @@ half of the pair, written as the signature [(+h, 1/2), (-h, 1/2)], and the
 diagonal of T_m(H) on the removed space is (1 - 1/c)(T_m(h) + T_m(-h))/2.
 Pendant-twin nodes are never twins of either kind.
 
+Hub paths (the figure's left panel at +-1/2): c >= 2 paths E - X - Y - F
+between the same two distinct nodes E, F, with X and Y of degree 2 and no
+other degree-2 neighbour (so the path has exactly two interior nodes).  On
+the differences between copies H couples each X to its Y with 1/2, so the
+X's and the Y's form two classes holding c - 1 eigenvalues at +1/2 and c - 1
+at -1/2, with the same paired signature as pendant twins.  The X side is the
+one adjacent to the smaller of the two end nodes.  These nodes are never
+twins or pendant twins.
+
 The paper detects them with a random hash w = Hz (equal w_i = w_j with high
 probability means equal neighbourhoods); here the oracle groups nodes by the
 exact key "sorted neighbour list" (a dict), so the partition is exact.
@@ -115,9 +124,41 @@ def pendant_classes(g) -> list:
     return out
 
 
+def hub_path_classes(g) -> list:
+    """Hub paths: pairs (X-class, Y-class), members ascending, for every pair
+    of end nodes E < F joined by >= 2 paths E - X - Y - F (deg X = deg Y = 2,
+    X's and Y's other neighbours not of degree 2, E != F)."""
+    deg = np.diff(g.row_ptr)
+    groups = {}
+    for x in range(g.n):
+        if deg[x] != 2:
+            continue
+        nb = g.neighbors(x).tolist()
+        two = [u for u in nb if deg[u] == 2]
+        if len(two) != 1:
+            continue
+        y = two[0]
+        e = nb[0] if nb[1] == y else nb[1]
+        ynb = g.neighbors(y).tolist()
+        f = ynb[0] if ynb[1] == x else ynb[1]
+        if deg[f] == 2 or e == f:
+            continue
+        if e < f:
+            groups.setdefault((e, f), ([], []))[0].append(x)
+        else:
+            groups.setdefault((f, e), ([], []))[1].append(x)
+    out = []
+    for key in sorted(groups):
+        xs, ys = groups[key]
+        if len(xs) >= 2:
+            out.append((sorted(xs), sorted(ys)))
+    return out
+
+
 def motif_classes(g, kinds) -> tuple:
-    """All classes of the requested kinds ("open", "closed", "pendants"), in
-    canonical order (by smallest member), with their signatures."""
+    """All classes of the requested kinds ("open", "closed", "pendants",
+    "hubpaths"), in canonical order (by smallest member), with their
+    signatures."""
     cls = []
     for kind in ("open", "closed"):
         if kind in kinds:
@@ -126,6 +167,9 @@ def motif_classes(g, kinds) -> tuple:
         for cb, ca, d in pendant_classes(g):
             h = float(np.sqrt(1.0 / d))   # 1/sqrt(d), correctly rounded
             cls += [(cb, [(h, 0.5), (-h, 0.5)]), (ca, [(h, 0.5), (-h, 0.5)])]
+    if "hubpaths" in kinds:
+        for cx, cy in hub_path_classes(g):
+            cls += [(cx, [(0.5, 0.5), (-0.5, 0.5)]), (cy, [(0.5, 0.5), (-0.5, 0.5)])]
     cls.sort(key=lambda t: t[0][0])
     return [c for c, _ in cls], [sgn for _, sgn in cls]
 

@@ -432,3 +432,84 @@ def test_paper_figure_pendant_panels(name, cb):
     sp = twins.spikes(cls, sig, g.n)
     assert [l for l, _ in sp] == pytest.approx(sorted(mo["lambda"]), abs=1e-15)
     assert [w for _, w in sp] == [1 / 9, 1 / 9]
+
+
+# ------------------------------------------------------------ hub paths
+def _hub_path_graph(seed):
+    # ER core plus groups of 2..4 two-node paths between random pairs of core nodes
+    n0, s, d = sg.erdos_renyi(80, 0.08, seed=seed)
+    rng = np.random.default_rng(seed)
+    ss, dd, nxt = list(s), list(d), n0
+    for _ in range(6):
+        e, f = (int(x) for x in rng.choice(n0, 2, replace=False))
+        for _ in range(int(rng.integers(2, 5))):
+            ss += [e, nxt, nxt + 1]
+            dd += [nxt, nxt + 1, f]
+            nxt += 2
+    return nxt, np.array(ss, np.int32), np.array(dd, np.int32)
+
+
+def brute_hub_paths(g):
+    deg = np.diff(g.row_ptr)
+    paths = {}
+    for x in range(g.n):
+        for y in g.neighbors(x).tolist():
+            if x < y and deg[x] == 2 and deg[y] == 2:
+                e = [u for u in g.neighbors(x).tolist() if u != y][0]
+                f = [u for u in g.neighbors(y).tolist() if u != x][0]
+                if e != f and deg[e] != 2 and deg[f] != 2:
+                    a, b = (x, y) if e < f else (y, x)
+                    paths.setdefault((min(e, f), max(e, f)), []).append((a, b))
+    return sorted((sorted(a for a, _ in v), sorted(b for _, b in v)) for v in paths.values() if len(v) >= 2)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_hub_paths_match_bruteforce_and_spectrum(seed):
+    g, H = graph_of(_hub_path_graph(seed))
+    assert sorted(twins.hub_path_classes(g)) == brute_hub_paths(g)
+    cls, sig = twins.motif_classes(g, {"open", "closed", "pendants", "hubpaths"})
+    members = [x for c in cls for x in c]
+    assert len(members) == len(set(members))      # the kinds never overlap
+    Hd = H.toarray()
+    lam_h = list(np.sort(np.linalg.eigvalsh(Hd)))
+    P = twins.basis_dense(cls, g.n)
+    lam_r = np.sort(np.linalg.eigvalsh(P.T @ Hd @ P))
+    sp = twins.spikes(cls, sig, g.n)
+    assert any(l == 0.5 for l, _ in sp) and any(l == -0.5 for l, _ in sp)
+    for lam, w in sp:
+        for _ in range(int(round(w * g.n))):
+            k = int(np.argmin(np.abs(np.array(lam_h) - lam)))
+            assert abs(lam_h[k] - lam) < 1e-10
+            lam_h.pop(k)
+    assert np.allclose(np.sort(lam_h), lam_r, atol=1e-10)
+
+
+def test_hub_path_filtered_estimates_unbiased_by_enumeration():
+    # three two-node paths between nodes 0 and 1, plus a pendant edge: 9 nodes
+    s = np.array([0, 2, 3, 0, 4, 5, 0, 6, 7, 1], np.int32)
+    d = np.array([2, 3, 1, 4, 5, 1, 6, 7, 1, 8], np.int32)
+    g, H = graph_of((9, s, d))
+    cls, sig = twins.motif_classes(g, {"open", "closed", "pendants", "hubpaths"})
+    assert [2, 4, 6] in cls and [3, 5, 7] in cls
+    Z = np.array(list(itertools.product([-1.0, 1.0], repeat=g.n))).T
+    M = 9
+    mu_full, _, _, C = twins.filtered_moments(H, Z, M, cls, lambdas=sig)
+    mu_x, l_x = kpm.exact_moments_eig(H, M)
+    assert np.allclose(mu_full, mu_x, atol=1e-12)
+    assert np.allclose(C, l_x, atol=1e-12)
+
+
+def test_paper_figure_hub_path_panel():
+    """The figure's left panel at +-1/2: two paths between the same two hubs."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "motif_spikes.txt")
+    mo = [m for m in _read_motifs(path) if m["name"] == "two_paths_between_hubs"][0]
+    _, hs, hd = sg.complete(5)
+    s = np.concatenate([hs, np.array([e[0] for e in mo["edges"]], np.int32)])
+    d = np.concatenate([hd, np.array([e[1] for e in mo["edges"]], np.int32)])
+    g, _ = graph_of((9, s, d))
+    cls, sig = twins.motif_classes(g, {"hubpaths"})
+    assert cls == [[5, 7], [6, 8]]
+    sp = twins.spikes(cls, sig, g.n)
+    assert [l for l, _ in sp] == sorted(mo["lambda"])
+    assert [w for _, w in sp] == [1 / 9, 1 / 9]
