@@ -77,6 +77,8 @@ typedef struct nd_motifs nd_motifs; /* twin classes found in a graph */
                                      neighbourhoods N(i) + {i} */
 #define ND_PENDANTS 0x4u          /* nd_motif_filter: pendant twins, nodes with one private
                                      leaf and equal remaining neighbourhoods */
+#define ND_HUBPATHS 0x8u          /* nd_motif_filter: >= 2 two-node paths between the same
+                                     two nodes */
 
 #define ND_KERNEL_NONE 0u         /* nd_reconstruct: plain truncated series */
 #define ND_KERNEL_JACKSON 1u      /* nd_reconstruct: Jackson damping factors */
@@ -137,13 +139,17 @@ void nd_graph_free(nd_graph* g);
  * at -1/sqrt(d) (d = 2: pendant paths E - B - A on one node E).  Candidates
  * are grouped by the same hash-and-verify scheme on N(B) minus the leaf.
  * Pendant-twin nodes are never twins.
+ * Hub paths (ND_HUBPATHS; the figure's left panel at +-1/2): c >= 2 paths
+ * E - X - Y - F between the same two distinct nodes (deg X = deg Y = 2, no
+ * other degree-2 neighbour) give two classes, the nodes next to the smaller
+ * end and the others, carrying c-1 eigenvalues at +1/2 and c-1 at -1/2.
  * Candidates come from a random hash of each neighbourhood,
  * h_i = sum_{j in N(i)} r_j (+ r_i for closed neighbourhoods) over Z/2^64 with
  * seeded random r (the paper hashes with w = Hz); every candidate class is
  * then confirmed by exact comparison of sorted neighbour lists, so the
  * partition does not depend on the seed.
  *   kinds  any non-empty combination of ND_TWINS_OPEN, ND_TWINS_CLOSED,
- *          ND_PENDANTS.
+ *          ND_PENDANTS, ND_HUBPATHS.
  * Output classes (size >= 2) are in canonical order: by smallest member,
  * members ascending.  Synchronises `stream`.
  * Errors: ND_EINVAL, ND_EUNSUPPORTED (other kinds), ND_ENOMEM, ND_EDEVICE. */
@@ -152,7 +158,8 @@ nd_status nd_motif_filter(const nd_graph* g, uint64_t seed, uint32_t kinds, void
 
 /* Counts and spikes (host outputs; any may be NULL).  A twin class C removes
  * |C|-1 eigenvalues at lambda_C (0 or -1/d); a pendant-twin class removes
- * (|C|-1)/2 at each of +-1/sqrt(d).  The spikes are the distinct removed eigenvalues
+ * (|C|-1)/2 at each of +-1/sqrt(d), a hub-path class (|C|-1)/2 at each of
+ * +-1/2.  The spikes are the distinct removed eigenvalues
  * in ascending order, each with its removed count over N (a fraction of the
  * DOS mass).  spike_lambda/spike_weight need room
  * for *n_spikes entries: call once with them NULL to learn the count. */
@@ -164,10 +171,10 @@ nd_status nd_motif_export(const nd_motifs* m, int64_t* class_ptr, int32_t* membe
 
 /* Host copies (either may be NULL) of each class's removed eigenvalue,
  * class_lambda double [n_classes]: 0 for open twins, -1/d for closed twins of
- * degree d, 1/sqrt(d) for pendant-twin classes (B's of degree d); and
- * class_paired int32 [n_classes]: 1 for pendant-twin classes (half of the
- * class's removed dimensions at +class_lambda, half at -class_lambda),
- * else 0. */
+ * degree d, 1/sqrt(d) for pendant-twin classes (B's of degree d), 1/2 for
+ * hub-path classes; and class_paired int32 [n_classes]: 1 for pendant-twin
+ * and hub-path classes (half of the class's removed dimensions at
+ * +class_lambda, half at -class_lambda), else 0. */
 nd_status nd_motif_export_lambda(const nd_motifs* m, double* class_lambda, int32_t* class_paired);
 
 void nd_motifs_free(nd_motifs* m);

@@ -27,6 +27,7 @@ ND_MOMENT_DOUBLING = 0x8
 ND_TWINS_OPEN = 0x1
 ND_TWINS_CLOSED = 0x2
 ND_PENDANTS = 0x4
+ND_HUBPATHS = 0x8
 ND_KERNEL_NONE, ND_KERNEL_JACKSON, ND_SPIKES_IN_MOMENTS = 0, 1, 0x10
 
 _STATUS = {ND_EINVAL: "ND_EINVAL", ND_ENOMEM: "ND_ENOMEM", ND_EDEVICE: "ND_EDEVICE",

