@@ -287,6 +287,17 @@ nd_status nd_gql(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes, i
                  uint64_t probe_seed, uint32_t flags, double* nodes, double* weights, int32_t* steps,
                  double* alpha, double* beta, void* stream);
 
+/* PDOS by GQL (Sec. 3.2 with z = e_v): for each listed node v, the K-node
+ * Gauss rule of the measure sum_i q_i(v)^2 delta(lambda - lambda_i) (its
+ * weights sum to 1), from K = n_steps Lanczos steps started at e_v.  Its
+ * Chebyshev moments are the exact PDOS moments T_m(H)_vv for m <= 2K-1.
+ *   vertices  device int32 [n_vertices], compact node ids
+ *   flags     optionally ND_STATE_FP64, ND_TIME_STEPS
+ *   nodes, weights, steps  as in nd_gql, one row per listed node.
+ * Synchronises `stream`; ND_EINVAL for ids out of range. */
+nd_status nd_gql_pdos(const nd_graph* g, const int32_t* vertices, int32_t n_vertices, int32_t n_steps,
+                      uint32_t flags, double* nodes, double* weights, int32_t* steps, void* stream);
+
 /* From the rules of nd_gql (device arrays [n_probes][n_steps]): Chebyshev
  * moments mu[m] = (1/k) sum_j sum_i w_ji T_m(tau_ji), m < n_moments (device
  * double, or NULL), and/or the histogram of the point masses over n_bins

@@ -39,7 +39,7 @@ EXPORTS = (
     "nd_graph_free",
     "nd_motif_filter", "nd_motif_info", "nd_motif_export", "nd_motif_export_lambda", "nd_motifs_free",
     "nd_make_probes",
-    "nd_cheb_moments", "nd_ldos_moments", "nd_pdos_nodes", "nd_gql", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_column_stats",
+    "nd_cheb_moments", "nd_ldos_moments", "nd_pdos_nodes", "nd_gql", "nd_gql_pdos", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_column_stats",
     "nd_mlp_forward", "nd_mlp_grad", "nd_adam_step", "nd_last_error",
 )
 
@@ -86,6 +86,7 @@ _sig("nd_cheb_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp])
 _sig("nd_ldos_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp, _vp])
 _sig("nd_pdos_nodes", [_vp, _vp, _i32, _i32, _u32, _vp, _vp])
 _sig("nd_gql", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp, _vp, _vp])
+_sig("nd_gql_pdos", [_vp, _vp, _i32, _i32, _u32, _vp, _vp, _vp, _vp])
 _sig("nd_gql_density", [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _dbl, _dbl, _vp, _vp])
 _sig("nd_reconstruct", [_vp, _i64, _i32, _u32, _vp, _vp, _i32, _i32, _dbl, _dbl, _vp, _i32, _vp, _vp])
 _sig("nd_last_error", [], ctypes.c_char_p)
@@ -308,6 +309,17 @@ def nd_gql(g: Graph, motifs, n_probes: int, n_steps: int, seed: int, flags: int,
     pb = _dev(beta, torch.float64, kk, "beta")
     _check(_lib.nd_gql(g.handle, _h(motifs), n_probes, n_steps, seed, flags, pn, pw, ps, pa, pb, _stream(stream)),
            "nd_gql")
+
+
+def nd_gql_pdos(g: Graph, vertices, n_steps: int, flags: int, nodes, weights, steps=None, stream=None):
+    """Gauss rules of the PDOS of the nodes in the device int32 tensor `vertices`."""
+    import torch
+    nv = int(vertices.numel())
+    pv = _dev(vertices, torch.int32, nv, "vertices")
+    pn = _dev(nodes, torch.float64, nv * n_steps, "nodes")
+    pw = _dev(weights, torch.float64, nv * n_steps, "weights")
+    ps = _dev(steps, torch.int32, nv, "steps")
+    _check(_lib.nd_gql_pdos(g.handle, pv, nv, n_steps, flags, pn, pw, ps, _stream(stream)), "nd_gql_pdos")
 
 
 def nd_gql_density(nodes, weights, n_probes: int, n_steps: int, n_moments: int = 0, mu=None, n_bins: int = 0,

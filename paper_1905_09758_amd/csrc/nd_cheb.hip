@@ -1296,10 +1296,12 @@ nd_status run_lanczos(nd_graph* g, const MomentJob& job, int K, double* alpha, d
     a.partial = partial;
     ND_CHECK(launch_step<T>(L, a, grid, true, st));
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, partial, bs.slots, per_step, 1, kp, kb, 0,
-                       1.0 / static_cast<double>(N), norm2, int64_t(1), static_cast<int64_t>(j0));
+                       job.unit_nodes ? 1.0 : 1.0 / static_cast<double>(N), norm2, int64_t(1),
+                       static_cast<int64_t>(j0));
     ND_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_lanczos_init, dim3(1), dim3(64), 0, st, kb, kp, static_cast<double>(N), norm2 + j0, lz,
-                       active);
+    // |z|^2 = norm2 N (norm2 is already |z|^2 for unit probes)
+    hipLaunchKernelGGL(k_lanczos_init, dim3(1), dim3(64), 0, st, kb, kp, job.unit_nodes ? 1.0 : static_cast<double>(N),
+                       norm2 + j0, lz, active);
     ND_LAUNCH_CHECK();
     a.zmode = 3;
     a.lz = lz;
@@ -1363,11 +1365,12 @@ nd_status check_common(const nd_graph* g, const nd_motifs* motifs, int32_t n_pro
 
 }  // namespace
 
-nd_status lanczos_coefficients(nd_graph* g, const nd_motifs* motifs, int32_t n_probes, int32_t n_steps, uint64_t seed,
-                               uint32_t flags, double* alpha, double* beta, double* norm2, int32_t* steps,
-                               hipStream_t st) {
+nd_status lanczos_coefficients(nd_graph* g, const nd_motifs* motifs, const int32_t* unit_nodes, int32_t n_probes,
+                               int32_t n_steps, uint64_t seed, uint32_t flags, double* alpha, double* beta,
+                               double* norm2, int32_t* steps, hipStream_t st) {
   MomentJob job;
   job.motifs = motifs;
+  job.unit_nodes = unit_nodes;
   job.k = n_probes;
   job.M = n_steps;
   job.seed = seed;

@@ -198,11 +198,12 @@ namespace nd {
 nd_status get_internal(nd_graph* g, hipStream_t st, Internal** out);
 nd_status get_schedule(nd_graph* g, int L, hipStream_t st, Schedule** out);
 // Lanczos coefficients of every probe (Sec. 3.2), on the sparse step kernels:
-// alpha, beta device [n_probes][n_steps], norm2 device [n_probes] (|z|^2/N),
-// steps device int32 [n_probes].
-nd_status lanczos_coefficients(nd_graph* g, const nd_motifs* motifs, int32_t n_probes, int32_t n_steps, uint64_t seed,
-                               uint32_t flags, double* alpha, double* beta, double* norm2, int32_t* steps,
-                               hipStream_t st);
+// alpha, beta device [n_probes][n_steps], norm2 device [n_probes] (|z|^2/N,
+// or 1 for unit probes), steps device int32 [n_probes].  With unit_nodes
+// (device int32 [n_probes]) probe j is the unit vector of that node.
+nd_status lanczos_coefficients(nd_graph* g, const nd_motifs* motifs, const int32_t* unit_nodes, int32_t n_probes,
+                               int32_t n_steps, uint64_t seed, uint32_t flags, double* alpha, double* beta,
+                               double* norm2, int32_t* steps, hipStream_t st);
 nd_status check_moment_args(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes, int32_t n_moments,
                             uint32_t flags, const char* who);
 }

@@ -119,6 +119,36 @@ __global__ __launch_bounds__(kBlock) void k_gql_hist(int k, int K, const double*
   }
 }
 
+// Lanczos coefficients, then one Gauss rule per probe (unit probes when
+// unit_nodes is given).
+nd_status gql_impl(const nd_graph* g, const nd_motifs* motifs, const int32_t* unit_nodes, int32_t n_probes,
+                   int32_t n_steps, uint64_t probe_seed, uint32_t flags, double* nodes, double* weights,
+                   int32_t* steps, double* alpha, double* beta, hipStream_t st) {
+  const size_t kk = static_cast<size_t>(n_probes) * n_steps;
+  Tmp t;
+  double *al = alpha, *be = beta, *norm2, *sub;
+  int32_t *stp = steps, *failed;
+  if (!al) ND_CHECK(t.get(&al, kk));
+  if (!be) ND_CHECK(t.get(&be, kk));
+  if (!stp) ND_CHECK(t.get(&stp, static_cast<size_t>(n_probes)));
+  ND_CHECK(t.get(&norm2, static_cast<size_t>(n_probes)));
+  ND_CHECK(t.get(&sub, kk));
+  ND_CHECK(t.get(&failed, 1));
+  ND_HIP(hipMemsetAsync(al, 0, kk * 8, st));
+  ND_HIP(hipMemsetAsync(be, 0, kk * 8, st));
+  ND_HIP(hipMemsetAsync(failed, 0, 4, st));
+  ND_CHECK(lanczos_coefficients(const_cast<nd_graph*>(g), motifs, unit_nodes, n_probes, n_steps, probe_seed, flags, al,
+                                be, norm2, stp, st));
+  hipLaunchKernelGGL(k_gql_rule, dim3(static_cast<unsigned>(ceil_div(n_probes, 64))), dim3(64), 0, st, n_probes,
+                     n_steps, al, be, norm2, stp, sub, nodes, weights, failed);
+  ND_LAUNCH_CHECK();
+  int32_t hf = 0;
+  ND_HIP(hipMemcpyAsync(&hf, failed, 4, hipMemcpyDeviceToHost, st));
+  ND_HIP(hipStreamSynchronize(st));
+  ND_REQUIRE(hf == 0, "nd_gql: the tridiagonal eigensolver did not converge for %d probes", hf);
+  return ND_OK;
+}
+
 }  // namespace
 }  // namespace nd
 
@@ -133,30 +163,27 @@ nd_status nd_gql(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes, i
   ND_REQUIRE((flags & ND_MOMENT_DOUBLING) == 0, "nd_gql: ND_MOMENT_DOUBLING does not apply");
   ND_REQUIRE(nodes != nullptr && weights != nullptr, "nd_gql: nodes/weights are NULL");
   ND_REQUIRE(n_steps <= 4096, "nd_gql: n_steps=%d exceeds 4096", n_steps);
+  return gql_impl(g, motifs, nullptr, n_probes, n_steps, probe_seed, flags, nodes, weights, steps, alpha, beta,
+                  as_stream(stream));
+}
+
+nd_status nd_gql_pdos(const nd_graph* g, const int32_t* vertices, int32_t n_vertices, int32_t n_steps,
+                      uint32_t flags, double* nodes, double* weights, int32_t* steps, void* stream) {
+  using namespace nd;
+  clear_error();
+  ND_CHECK(check_moment_args(g, nullptr, n_vertices, n_steps, flags, "nd_gql_pdos"));
+  ND_REQUIRE((flags & ~(ND_STATE_FP64 | ND_TIME_STEPS)) == 0, "nd_gql_pdos: flags 0x%x (only ND_STATE_FP64, "
+             "ND_TIME_STEPS apply)", flags);
+  ND_REQUIRE(vertices != nullptr && nodes != nullptr && weights != nullptr, "nd_gql_pdos: NULL argument");
+  ND_REQUIRE(n_steps <= 4096, "nd_gql_pdos: n_steps=%d exceeds 4096", n_steps);
   hipStream_t st = as_stream(stream);
-  const size_t kk = static_cast<size_t>(n_probes) * n_steps;
-  Tmp t;
-  double *al = alpha, *be = beta, *norm2, *sub;
-  int32_t *stp = steps, *failed;
-  if (!al) ND_CHECK(t.get(&al, kk));
-  if (!be) ND_CHECK(t.get(&be, kk));
-  if (!stp) ND_CHECK(t.get(&stp, static_cast<size_t>(n_probes)));
-  ND_CHECK(t.get(&norm2, static_cast<size_t>(n_probes)));
-  ND_CHECK(t.get(&sub, kk));
-  ND_CHECK(t.get(&failed, 1));
-  ND_HIP(hipMemsetAsync(al, 0, kk * 8, st));
-  ND_HIP(hipMemsetAsync(be, 0, kk * 8, st));
-  ND_HIP(hipMemsetAsync(failed, 0, 4, st));
-  ND_CHECK(lanczos_coefficients(const_cast<nd_graph*>(g), motifs, n_probes, n_steps, probe_seed, flags, al, be, norm2,
-                                stp, st));
-  hipLaunchKernelGGL(k_gql_rule, dim3(static_cast<unsigned>(ceil_div(n_probes, 64))), dim3(64), 0, st, n_probes,
-                     n_steps, al, be, norm2, stp, sub, nodes, weights, failed);
-  ND_LAUNCH_CHECK();
-  int32_t hf = 0;
-  ND_HIP(hipMemcpyAsync(&hf, failed, 4, hipMemcpyDeviceToHost, st));
-  ND_HIP(hipStreamSynchronize(st));
-  ND_REQUIRE(hf == 0, "nd_gql: the tridiagonal eigensolver did not converge for %d probes", hf);
-  return ND_OK;
+  {
+    std::vector<int32_t> h(static_cast<size_t>(n_vertices));
+    ND_HIP(hipMemcpyAsync(h.data(), vertices, h.size() * 4, hipMemcpyDeviceToHost, st));
+    ND_HIP(hipStreamSynchronize(st));
+    for (int32_t v : h) ND_REQUIRE(v >= 0 && v < g->n, "nd_gql_pdos: node id %d not in [0, %lld)", v, (long long)g->n);
+  }
+  return gql_impl(g, nullptr, vertices, n_vertices, n_steps, 0, flags, nodes, weights, steps, nullptr, nullptr, st);
 }
 
 nd_status nd_gql_density(const double* nodes, const double* weights, int32_t n_probes, int32_t n_steps,

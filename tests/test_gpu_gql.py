@@ -121,3 +121,30 @@ def test_gql_errors(nd):
         nd.nd_gql(g, None, 2, 0, 1, 0, buf, buf)
     with pytest.raises(nd.NDError):
         nd.nd_gql_density(buf, buf, 2, 4)
+
+
+@pytest.mark.parametrize("state", ["fp32", "fp64"])
+def test_gql_pdos_unit_probes(nd, state):
+    """GQL from e_v (Sec. 3.2): the rule's moments are the exact PDOS moments
+    of v up to degree 2K-1; weights sum to 1."""
+    import torch
+    n, s, d = sg.barabasi_albert(1500, 2, seed=3, twin_pairs=20)
+    g_or = og.build_csr(n, s, d)
+    g = nd.nd_build_csr(n, s, d)
+    K = 10
+    _, l_x = kpm.exact_moments_eig(og.normalized_adjacency(g_or), 2 * K)
+    rng = np.random.default_rng(4)
+    sel = np.concatenate([[int(np.argmax(g_or.deg))], rng.choice(g_or.n, 69, replace=False)]).astype(np.int32)
+    kk = sel.size * K
+    nodes = torch.zeros(kk, dtype=torch.float64, device="cuda")
+    weights = torch.zeros(kk, dtype=torch.float64, device="cuda")
+    steps = torch.zeros(sel.size, dtype=torch.int32, device="cuda")
+    flags = nd.ND_STATE_FP64 if state == "fp64" else 0
+    nd.nd_gql_pdos(g, torch.from_numpy(sel).cuda(), K, flags, nodes, weights, steps)
+    n_, w_, s_ = (x.cpu().numpy() for x in (nodes, weights, steps))
+    n_, w_ = n_.reshape(sel.size, K), w_.reshape(sel.size, K)
+    tol = 1e-9 if state == "fp64" else 1e-5
+    for j, v in enumerate(sel):
+        rule = [(n_[j, :s_[j]], w_[j, :s_[j]])]
+        assert abs(w_[j].sum() - 1.0) < 1e-9
+        assert np.max(np.abs(gql.gql_moments(rule, 2 * K) - l_x[v, :2 * K])) < tol
