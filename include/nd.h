@@ -256,6 +256,29 @@ nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
 nd_status nd_pdos_nodes(const nd_graph* g, const int32_t* nodes, int32_t n_nodes, int32_t n_moments, uint32_t flags,
                         double* pdos, void* stream);
 
+/* Exact PDOS moments of every node by nested dissection (Sec. 3.3,
+ * Algorithm 1, eqn ndchebsep): a nested-dissection tree of the graph, then
+ * for every tree node the columns of T_m(H) at its separator restricted to
+ * its partition, by the block recurrence with the couplings through the
+ * ancestors' separators; the diagonals give T_m(H)_vv for all v.
+ * The tree comes from recursive bisection on BFS level structures
+ * (separators are BFS levels; components split with an empty separator),
+ * stopping at partitions of at most leaf_size nodes.  Block entries are
+ * fp64.
+ *   n_moments    >= 1
+ *   leaf_size    1..4096
+ *   max_entries  cap on the total block entries sum_t |I_p| |I_s| (two fp64
+ *                buffers of that size are allocated)
+ *   flags        optionally ND_TIME_STEPS (per-moment launches)
+ *   pdos         device double [N][n_moments], row-major
+ *   stats        host int64 [4] or NULL: tree nodes, depth, separator
+ *                nodes, block entries
+ * Synchronises `stream`.  ND_EUNSUPPORTED when the graph has no small
+ * separators (a partition over 4096 nodes without a separator, or more
+ * block entries than max_entries). */
+nd_status nd_pdos_nested(const nd_graph* g, int32_t n_moments, int32_t leaf_size, int64_t max_entries,
+                         uint32_t flags, double* pdos, int64_t* stats, void* stream);
+
 /* --------------------------------------------------------------- GQL */
 
 /* Gauss quadrature and Lanczos (Sec. 3.2).  For every probe z_j (the same

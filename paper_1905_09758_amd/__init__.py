@@ -39,7 +39,7 @@ EXPORTS = (
     "nd_graph_free",
     "nd_motif_filter", "nd_motif_info", "nd_motif_export", "nd_motif_export_lambda", "nd_motifs_free",
     "nd_make_probes",
-    "nd_cheb_moments", "nd_ldos_moments", "nd_pdos_nodes", "nd_gql", "nd_gql_pdos", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_column_stats",
+    "nd_cheb_moments", "nd_ldos_moments", "nd_pdos_nodes", "nd_pdos_nested", "nd_gql", "nd_gql_pdos", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_column_stats",
     "nd_mlp_forward", "nd_mlp_grad", "nd_adam_step", "nd_last_error",
 )
 
@@ -85,6 +85,7 @@ _sig("nd_make_probes", [_vp, _vp, _i32, _u64, _u32, _vp, _vp])
 _sig("nd_cheb_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp])
 _sig("nd_ldos_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp, _vp])
 _sig("nd_pdos_nodes", [_vp, _vp, _i32, _i32, _u32, _vp, _vp])
+_sig("nd_pdos_nested", [_vp, _i32, _i32, _i64, _u32, _vp, _vp, _vp])
 _sig("nd_gql", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("nd_gql_pdos", [_vp, _vp, _i32, _i32, _u32, _vp, _vp, _vp, _vp])
 _sig("nd_gql_density", [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _dbl, _dbl, _vp, _vp])
@@ -296,6 +297,18 @@ def nd_pdos_nodes(g: Graph, nodes, n_moments: int, flags: int, pdos, stream=None
     pn = _dev(nodes, torch.int32, n, "nodes")
     pp = _dev(pdos, torch.float64, n * n_moments, "pdos")
     _check(_lib.nd_pdos_nodes(g.handle, pn, n, n_moments, flags, pp, _stream(stream)), "nd_pdos_nodes")
+
+
+def nd_pdos_nested(g: Graph, n_moments: int, pdos, leaf_size: int = 64, max_entries: int = 1 << 30,
+                   flags: int = 0, stream=None) -> dict:
+    """Exact PDOS moments of all nodes by nested dissection; returns the
+    partition statistics."""
+    import torch
+    pp = _dev(pdos, torch.float64, g.n * n_moments, "pdos")
+    st = np.zeros(4, np.int64)
+    _check(_lib.nd_pdos_nested(g.handle, n_moments, leaf_size, max_entries, flags, pp, st.ctypes.data,
+                               _stream(stream)), "nd_pdos_nested")
+    return {"tree_nodes": int(st[0]), "depth": int(st[1]), "separator_nodes": int(st[2]), "block_entries": int(st[3])}
 
 
 def nd_gql(g: Graph, motifs, n_probes: int, n_steps: int, seed: int, flags: int, nodes, weights, steps=None,

@@ -185,3 +185,12 @@ def plant_adjacent_pairs(n: int, src, dst, pairs: int, seed: int, hubs=(1, 2, 3)
     src = np.concatenate([np.asarray(src, np.int32), np.asarray(s_add, np.int32)])
     dst = np.concatenate([np.asarray(dst, np.int32), np.asarray(d_add, np.int32)])
     return n + 2 * pairs, src, dst
+
+
+def grid2d(nx: int, ny: int):
+    """nx x ny lattice, node (i, j) = i * ny + j, 4-neighbour edges."""
+    i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    node = (i * ny + j).astype(np.int32)
+    s = np.concatenate([node[:-1, :].ravel(), node[:, :-1].ravel()])
+    d = np.concatenate([node[1:, :].ravel(), node[:, 1:].ravel()])
+    return nx * ny, s.astype(np.int32), d.astype(np.int32)
