@@ -243,7 +243,7 @@ def nested_study(args) -> dict:
 
 
 def cv_study(args) -> dict:
-    """Learned control variate (config 5): train on synthetic graphs of four
+    """Learned control variate study: train on synthetic graphs of four
     families with LDOS targets from the method itself, then compare the
     probes needed for a per-node, per-moment variance of 1e-3 on held-out
     graphs: plain Rademacher, plain Gaussian, Gaussian with the learned
@@ -362,8 +362,8 @@ def main():
     if args.gql and args.doubling:
         ap.error("--gql and --doubling are exclusive")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the hot path shards by probes, "
-              "see the design notes); --gpus must be 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU (sharding the probe blocks across GPUs is not "
+              "implemented); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
