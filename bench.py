@@ -460,7 +460,8 @@ def main():
     avg_launch_ms = kern_ms / max(kern_n, 1)
     b_launch = algorithmic_bytes(n, nnz, k, W.ldos, own_row=bool(not W.ldos and (args.doubling or args.gql)))
     achieved = b_launch / (avg_launch_ms * 1e-3) / 1e9
-    traffic = profiled_traffic(args.workload)
+    # the counter records are of the plain Chebyshev step launches
+    traffic = profiled_traffic(args.workload) if not (args.doubling or args.gql) else None
     copy_gbs = copy_bandwidth_gbs()
     mu = out["mu"].cpu().numpy()
     line = {
