@@ -5,7 +5,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 
 #include "nd_common.h"
 
@@ -33,6 +36,64 @@ static size_t alloc_limit() {
   return lim;
 }
 
+// Device memory is cached per device: freed blocks stay mapped in a pool and
+// are handed out again to requests of their size class (graphs rebuilt in a
+// loop, workspaces regrown, temporaries of every call), so the steady state
+// makes no hipMalloc/hipFree calls.  A cached block is reused only after the
+// device has drained (hipDeviceSynchronize), so work still queued on any
+// stream never sees its memory change hands.  When hipMalloc fails, the cache
+// is released and the allocation retried.  The pool lives until the process
+// ends; ND_POOL_BYTES caps the cached total (default 32 GiB).
+namespace {
+
+struct Pool {
+  std::mutex mu;
+  std::map<int, std::multimap<size_t, void*>> free_blocks;  // device -> (size class, block)
+  std::unordered_map<void*, std::pair<int, size_t>> owned;  // block -> (device, size class)
+  size_t cached = 0;
+};
+
+Pool& pool() {
+  static Pool* p = new Pool();  // never destroyed: no HIP calls after the runtime shuts down
+  return *p;
+}
+
+size_t pool_cap() {
+  static size_t cap = [] {
+    const char* e = std::getenv("ND_POOL_BYTES");
+    return e ? static_cast<size_t>(std::strtoull(e, nullptr, 10)) : (size_t(32) << 30);
+  }();
+  return cap;
+}
+
+// Size classes: powers of two up to 1 MiB, then multiples of 2 MiB.
+size_t size_class(size_t bytes) {
+  if (bytes <= (size_t(1) << 20)) {
+    size_t c = 256;
+    while (c < bytes) c <<= 1;
+    return c;
+  }
+  const size_t g = size_t(2) << 20;
+  return (bytes + g - 1) / g * g;
+}
+
+void release_cached(Pool& P) {
+  for (auto& dev : P.free_blocks) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(dev.first);
+    for (auto& kv : dev.second) {
+      P.owned.erase(kv.second);
+      (void)hipFree(kv.second);
+    }
+    dev.second.clear();
+    (void)hipSetDevice(cur);
+  }
+  P.cached = 0;
+}
+
+}  // namespace
+
 nd_status dalloc(void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 1;
@@ -41,18 +102,73 @@ nd_status dalloc(void** p, size_t bytes) {
     set_error("allocation of %zu bytes exceeds ND_ALLOC_LIMIT_BYTES=%zu", bytes, lim);
     return ND_ENOMEM;
   }
-  hipError_t e = hipMalloc(p, bytes);
+  const size_t cls = size_class(bytes);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipGetDevice failed");
+    return ND_EDEVICE;
+  }
+  Pool& P = pool();
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto& fl = P.free_blocks[dev];
+    // small classes match exactly; large ones take a block up to twice the size
+    auto it = fl.lower_bound(cls);
+    if (it != fl.end() && (it->first == cls || (cls > (size_t(1) << 20) && it->first <= 2 * cls))) {
+      void* q = it->second;
+      P.cached -= it->first;
+      fl.erase(it);
+      if (hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        P.owned.erase(q);
+        (void)hipFree(q);
+        set_error("hipDeviceSynchronize failed before reusing device memory");
+        return ND_EDEVICE;
+      }
+      *p = q;
+      return ND_OK;
+    }
+  }
+  hipError_t e = hipMalloc(p, cls);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    *p = nullptr;
-    set_error("hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
-    return ND_ENOMEM;
+    std::lock_guard<std::mutex> lk(P.mu);
+    if (P.cached > 0) {
+      (void)hipDeviceSynchronize();
+      release_cached(P);
+      e = hipMalloc(p, cls);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      set_error("hipMalloc(%zu bytes): %s", cls, hipGetErrorString(e));
+      return ND_ENOMEM;
+    }
   }
+  std::lock_guard<std::mutex> lk(P.mu);
+  P.owned[*p] = {dev, cls};
   return ND_OK;
 }
 
 void dfree(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  auto it = P.owned.find(p);
+  if (it == P.owned.end()) {
+    (void)hipFree(p);
+    return;
+  }
+  const int dev = it->second.first;
+  const size_t cls = it->second.second;
+  if (P.cached + cls > pool_cap()) {
+    P.owned.erase(it);
+    (void)hipFree(p);
+    return;
+  }
+  P.free_blocks[dev].emplace(cls, p);
+  P.cached += cls;
 }
 
 namespace {
