@@ -141,6 +141,9 @@ struct StepArgs {
   int split_blocks; // grid of the split-row finisher; its slots follow the step kernel's
   double* ldos;     // [n][ld] (compact node order) or null
   double* ldos_sq;  // [n][ld] or null
+  double* stage;    // with ldos: [S][n] LDOS terms of S consecutive launches by internal row
+  double* stage_sq; // with ldos_sq: the same for the squares
+  int stage_pos;    // row of the staging block written by this launch
   int64_t ld;       // leading dimension of ldos / cv_g (= number of moments)
   int accumulate;   // add to ldos instead of overwriting (later probe blocks)
   const float* cv_g;
@@ -159,12 +162,15 @@ constexpr bool kOwnRow = ZM == 2 || ZM == 3;
 // Per-row epilogue: given Y_m(i, probes of this lane) in fp64 and the probe
 // values z, form the estimator terms v_ij = z_ij y_ij (+ g_im (1 - z_ij^2)
 // with a control variate), add them to this lane's per-probe sums (kept in
-// LDS: mom[c * kBlock] for probe c of the lane), and write
-// the row's LDOS entry.  Called by every lane of the wavefront; `own` selects
-// the lanes that hold a row's values.
+// LDS: mom[c * kBlock] for probe c of the lane), and write the row's LDOS
+// term to the staging block (by internal row, so that the rows of a
+// wavefront write one contiguous segment; k_ldos_flush moves a block of
+// launches into the [n][M] output).  Called by every lane of the wavefront;
+// `own` selects the lanes that hold a row's values.
 template <typename T, int L>
-__device__ inline void emit_moments(const StepArgs& a, bool own, int64_t node, const double (&y)[16 / sizeof(T)],
-                                    const T (&z)[16 / sizeof(T)], int q, double* mom) {
+__device__ inline void emit_moments(const StepArgs& a, bool own, int64_t r, int64_t node,
+                                    const double (&y)[16 / sizeof(T)], const T (&z)[16 / sizeof(T)], int q,
+                                    double* mom) {
   constexpr int PPL = 16 / sizeof(T);
   double s1 = 0.0, s2 = 0.0;
   if (own) {
@@ -187,12 +193,9 @@ __device__ inline void emit_moments(const StepArgs& a, bool own, int64_t node, c
       s2 += __shfl_xor(s2, off, kWave);
     }
     if (own && q == 0) {
-      double* p = a.ldos + node * a.ld + a.m;
-      *p = (a.accumulate ? *p : 0.0) + s1 * a.inv_k;
-      if (a.ldos_sq) {
-        double* p2 = a.ldos_sq + node * a.ld + a.m;
-        *p2 = (a.accumulate ? *p2 : 0.0) + s2 * a.inv_k;
-      }
+      const int64_t t = static_cast<int64_t>(a.stage_pos) * a.n + r;
+      a.stage[t] = s1 * a.inv_k;
+      if (a.ldos_sq) a.stage_sq[t] = s2 * a.inv_k;
     }
   }
 }
@@ -330,7 +333,7 @@ __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_
   } else {
     T z[PPL];
     row_probes<T, ZM>(a, own, r, q, o, z);
-    emit_moments<T, L>(a, own, o.node, y, z, q, mom);
+    emit_moments<T, L>(a, own, r, o.node, y, z, q, mom);
   }
 }
 
@@ -366,9 +369,22 @@ __device__ inline void gather_sum(const StepArgs& a, int64_t e0, int64_t e1, int
   }
 }
 
+// Column indices of the first gather batch of a row slice: nonzeros
+// e0+sub, e0+sub+P, ... (U of them, -1 past e1).
+template <int P, int U>
+__device__ inline void load_cols(const StepArgs& a, int64_t e0, int64_t e1, int sub, int32_t (&j)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t en = e0 + sub + u * P;
+    j[u] = (en < e1) ? __builtin_nontemporal_load(a.col + en) : -1;
+  }
+}
+
 // All items of one bin handled by this wavefront (items w, w+W, ...): P
-// nonzero slots per row, 64/(P*L) consecutive rows per item.  The row
-// pointers of item i+1 load while item i gathers.
+// nonzero slots per row, 64/(P*L) consecutive rows per item.  Software
+// pipelined: while item i gathers, the column indices of item i+W and the
+// row pointers of item i+2W load, so each item waits for one dependent
+// memory round trip (the gathers) instead of two.
 template <typename T, int L, int P, int U, int ZM>
 __device__ inline void rows_bin(const StepArgs& a, int bin, int64_t w, int64_t W, int lane, double* mom) {
   constexpr int PPL = 16 / sizeof(T);
@@ -387,19 +403,39 @@ __device__ inline void rows_bin(const StepArgs& a, int bin, int64_t w, int64_t W
       e0 = e1 = 0;
     }
   };
-  int64_t e0, e1;
+  const T* xg = reinterpret_cast<const T*>(a.xg) + q * PPL;
+  int64_t e0, e1, e0n, e1n;
   rp(w, e0, e1);
+  rp(w + W, e0n, e1n);
+  int32_t j[U];
+  load_cols<P, U>(a, e0, e1, sub, j);
   for (int64_t li = w; li < items; li += W) {
     const int64_t r = rs + li * RPW + grp;
     const bool own = r < re && sub == 0;
     RowOperands<T, ZM> o;
     load_row_operands<T, ZM>(a, own, r, q, o);
-    int64_t e0n, e1n;
-    rp(li + W, e0n, e1n);
+    T v[U][PPL];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j[u] >= 0) {
+        load16<T>(xg + static_cast<int64_t>(j[u]) * a.kp, v[u]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < PPL; ++c) v[u][c] = T(0);
+      }
+    }
+    load_cols<P, U>(a, e0n, e1n, sub, j);
+    int64_t e0nn, e1nn;
+    rp(li + 2 * W, e0nn, e1nn);
     T acc[PPL];
 #pragma unroll
     for (int c = 0; c < PPL; ++c) acc[c] = T(0);
-    gather_sum<T, P, U>(a, e0, e1, sub, q, acc);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < PPL; ++c) acc[c] += v[u][c];
+    // rows longer than one batch (the widest bin only)
+    if (e0 + sub + U * P < e1) gather_sum<T, P, U>(a, e0 + U * P, e1, sub, q, acc);
 #pragma unroll
     for (int off = L; off < G; off <<= 1)
 #pragma unroll
@@ -407,6 +443,8 @@ __device__ inline void rows_bin(const StepArgs& a, int bin, int64_t w, int64_t W
     finish_row<T, L, ZM, T>(a, own, r, e1 - e0, acc, o, q, mom);
     e0 = e0n;
     e1 = e1n;
+    e0n = e0nn;
+    e1n = e1nn;
   }
 }
 
@@ -493,8 +531,11 @@ __global__ __launch_bounds__(kBlock) void k_split_finish(StepArgs a, int step_gr
   block_partials<T, L, NS>(b, s_mom);
 }
 
+// Four wavefronts per SIMD: the software-pipelined gather loop needs more
+// than 128 VGPRs in the narrowest instantiations, where a few spilled
+// registers cost less than a lost wavefront.
 template <typename T, int L, int U, int ZM>
-__global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_cheb_step(StepArgs a) {
   constexpr int PPL = 16 / sizeof(T);
   constexpr int PMAX = kWave / L;
   constexpr int NS = kSums<ZM>;
@@ -557,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_moment0(StepArgs a) {
     double y[PPL];
 #pragma unroll
     for (int c = 0; c < PPL; ++c) y[c] = static_cast<double>(z[c]);
-    emit_moments<T, L>(a, own, o.node, y, z, q, mom);
+    emit_moments<T, L>(a, own, r, o.node, y, z, q, mom);
   }
   // no split rows at moment 0: clear the finisher's slots
   double* sp = a.partial + static_cast<int64_t>(gridDim.x) * a.kp;
@@ -742,6 +783,34 @@ __global__ __launch_bounds__(kBlock) void k_mu_final(const double* __restrict__ 
     double add = 0.0;
     for (int s = 0; s < n_spikes; ++s) add += spikes[n_spikes + s] * cheb_T(m, spikes[s]);
     mu[m] = (sum + comp) / static_cast<double>(k) + add;
+  }
+}
+
+// Moves the LDOS terms of launches m0 .. m0+S-1 from the staging block
+// ([S][n] by internal row) into the output ([n][ld] by compact node, columns
+// m0 ..), adding to what is there for the later probe blocks.  A block takes
+// 64 internal rows: the tile is read along rows and written S contiguous
+// entries per node, through LDS.
+constexpr int kFlushRows = 64;
+constexpr int kMaxStage = 32;
+
+__global__ __launch_bounds__(kBlock) void k_ldos_flush(const double* __restrict__ stage, int64_t n, int S,
+                                                       const int32_t* __restrict__ perm, double* __restrict__ out,
+                                                       int64_t ld, int m0, int accumulate) {
+  __shared__ double tile[kMaxStage][kFlushRows + 1];
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kFlushRows;
+  for (int t = threadIdx.x; t < S * kFlushRows; t += kBlock) {
+    const int s = t / kFlushRows, rr = t % kFlushRows;
+    const int64_t r = r0 + rr;
+    tile[s][rr] = r < n ? stage[static_cast<int64_t>(s) * n + r] : 0.0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < S * kFlushRows; t += kBlock) {
+    const int rr = t / S, s = t % S;
+    const int64_t r = r0 + rr;
+    if (r >= n) continue;
+    double* p = out + static_cast<int64_t>(perm[r]) * ld + m0 + s;
+    *p = (accumulate ? *p : 0.0) + tile[s][rr];
   }
 }
 
@@ -1063,8 +1132,20 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     double* partial = g->ws_partial.as<double>();
     // unit probes: z^T T_m(H) z is the PDOS moment itself, no 1/N
     const double inv_n = job.unit_nodes ? 1.0 : 1.0 / static_cast<double>(N);
+    // LDOS terms go through a staging block of S launches (at most 1 GiB)
+    int S = 0;
+    if (job.ldos) {
+      const int64_t per_launch = N * 8 * (job.ldos_sq ? 2 : 1);
+      const int64_t cap = (int64_t(1) << 30) / per_launch;
+      S = static_cast<int>(cap < kMaxStage ? (cap < 1 ? 1 : cap) : kMaxStage);
+      if (S > last + 1) S = last + 1;
+      ND_CHECK(g->ws_stage.ensure(static_cast<size_t>(S) * per_launch));
+      a.stage = g->ws_stage.as<double>();
+      a.stage_sq = job.ldos_sq ? a.stage + static_cast<int64_t>(S) * N : nullptr;
+    }
     for (int m = 0; m <= last; ++m) {
       a.m = m;
+      if (S) a.stage_pos = m % S;
       // ring position of this launch's partials; with doubling, moment 0 is
       // reduced on its own right away (one sum per probe) and the ring
       // starts at launch 1
@@ -1097,6 +1178,18 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
         }
         ND_CHECK(launch_step<T>(L, a, grid, false, st));
         if (job.timed) ND_HIP(hipEventRecord(e1, st));
+      }
+      if (S && (a.stage_pos + 1 == S || m == last)) {
+        const int nst = a.stage_pos + 1;
+        const unsigned fgrid = static_cast<unsigned>(ceil_div(N, kFlushRows));
+        hipLaunchKernelGGL(k_ldos_flush, dim3(fgrid), dim3(kBlock), 0, st, a.stage, N, nst, a.perm, job.ldos,
+                           static_cast<int64_t>(M), m + 1 - nst, a.accumulate);
+        ND_LAUNCH_CHECK();
+        if (job.ldos_sq) {
+          hipLaunchKernelGGL(k_ldos_flush, dim3(fgrid), dim3(kBlock), 0, st, a.stage_sq, N, nst, a.perm,
+                             job.ldos_sq, static_cast<int64_t>(M), m + 1 - nst, a.accumulate);
+          ND_LAUNCH_CHECK();
+        }
       }
       if (pos + 1 == R || m == last) {
         const int m0 = m - pos;
