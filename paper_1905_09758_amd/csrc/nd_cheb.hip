@@ -913,6 +913,20 @@ int max_block_probes() {
   return v;
 }
 
+// Launches per LDOS staging block: at most kMaxStage, fewer when the block
+// would exceed 1 GiB; ND_LDOS_STAGE lowers the maximum (read on every call;
+// tests use it to check that the grouping leaves the results unchanged).
+int ldos_stage_launches(int64_t bytes_per_launch, int launches) {
+  int smax = kMaxStage;
+  if (const char* e = std::getenv("ND_LDOS_STAGE")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v < smax) smax = v;
+  }
+  const int64_t cap = (int64_t(1) << 30) / bytes_per_launch;
+  int S = static_cast<int>(cap < smax ? (cap < 1 ? 1 : cap) : smax);
+  return S > launches ? launches : S;
+}
+
 struct MomentJob {
   const nd_motifs* motifs = nullptr;
   int k = 0, M = 0;
@@ -1136,9 +1150,7 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     int S = 0;
     if (job.ldos) {
       const int64_t per_launch = N * 8 * (job.ldos_sq ? 2 : 1);
-      const int64_t cap = (int64_t(1) << 30) / per_launch;
-      S = static_cast<int>(cap < kMaxStage ? (cap < 1 ? 1 : cap) : kMaxStage);
-      if (S > last + 1) S = last + 1;
+      S = ldos_stage_launches(per_launch, last + 1);
       ND_CHECK(g->ws_stage.ensure(static_cast<size_t>(S) * per_launch));
       a.stage = g->ws_stage.as<double>();
       a.stage_sq = job.ldos_sq ? a.stage + static_cast<int64_t>(S) * N : nullptr;

@@ -377,6 +377,28 @@ def test_filtered_moments(case, nd):
     assert np.max(np.abs(Zd.cpu().numpy().reshape(g.n, k) - Zr)) < 1e-7
 
 
+def test_ldos_stage_grouping(case, nd, monkeypatch):
+    """The LDOS terms pass through a staging block of S launches; any S
+    (several flushes, a partial last one, two probe blocks accumulating)
+    gives bit-identical LDOS and squared terms."""
+    import torch
+    name, _, g_or, g = case
+    k, M = 70, 45
+    outs = []
+    for stage in (None, "1", "4", "7"):
+        if stage is None:
+            monkeypatch.delenv("ND_LDOS_STAGE", raising=False)
+        else:
+            monkeypatch.setenv("ND_LDOS_STAGE", stage)
+        ld = _zeros(g.n * M, torch.float64)
+        sq = _zeros(g.n * M, torch.float64)
+        nd.nd_ldos_moments(g, None, k, M, 5, 0, ld, ldos_sq=sq)
+        outs.append((ld.cpu().numpy().tobytes(), sq.cpu().numpy().tobytes()))
+    monkeypatch.delenv("ND_LDOS_STAGE", raising=False)
+    for o in outs[1:]:
+        assert o == outs[0]
+
+
 def test_control_variate_ldos(case, nd):
     import torch
     name, _, g_or, g = case
