@@ -236,7 +236,13 @@ nd_status nd_cheb_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
  *   ldos     device double [N][n_moments]
  *   ldos_sq  NULL, or device double [N][n_moments]: (1/k) sum_j v_ijm^2,
  *            for the per-probe variance ldos_sq - ldos^2.
- *   mu       NULL, or device double [n_moments]: mean over nodes of ldos. */
+ *   mu       NULL, or device double [n_moments]: mean over nodes of ldos.
+ * Workspace: besides the recurrence state, the graph keeps a staging block of
+ * up to 32 launches' LDOS terms (8 bytes per node and launch, twice with
+ * ldos_sq, at most 1 GiB); the output rows are written 32 moments at a time.
+ * Errors: ND_EINVAL for NULL ldos, a graph without nodes, foreign motifs,
+ * unknown flags or ND_MOMENT_DOUBLING (global moments only); ND_ENOMEM when
+ * the workspace cannot be allocated. */
 nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes,
                           int32_t n_moments, uint64_t probe_seed, uint32_t flags,
                           const float* cv_g, double* ldos, double* ldos_sq, double* mu,
