@@ -98,6 +98,35 @@ __device__ inline float rademacher_entry(uint64_t seed, int64_t j, int64_t node)
   return (splitmix64(key, static_cast<uint64_t>(node) + 1) >> 63) ? -1.0f : 1.0f;
 }
 
+// One DPP lane permutation of a double (two 32-bit moves): CTRL 0xB1 and
+// 0x4E are the quad permutations [1,0,3,2] and [2,3,0,1] (lane xor 1, xor 2),
+// 0x141 mirrors each half row of 8 lanes, 0x140 each row of 16.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffull), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                                     static_cast<unsigned>(lo)));
+}
+
+// Sum of v over each aligned group of G lanes (G a power of two), every lane
+// of a group receiving the sum.  Within 16 lanes the partners come from DPP
+// permutations; after the quad steps all lanes of a quad hold the same bits,
+// so the mirrors pair each lane with a lane of the neighbouring quad / half
+// row exactly as lane xor 4 / xor 8 would.  Wider groups continue with
+// LDS-routed lane shuffles.  Every lane of the wavefront must be active.
+template <int G>
+__device__ inline double group_sum(double v) {
+  if constexpr (G >= 2) v += dpp_f64<0xB1>(v);
+  if constexpr (G >= 4) v += dpp_f64<0x4E>(v);
+  if constexpr (G >= 8) v += dpp_f64<0x141>(v);
+  if constexpr (G >= 16) v += dpp_f64<0x140>(v);
+#pragma unroll
+  for (int off = 16; off < G; off <<= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
 // Neumaier-compensated accumulation.
 __device__ inline void neumaier(double& s, double& c, double x) {
   const double t = s + x;
@@ -187,11 +216,8 @@ __device__ inline void emit_moments(const StepArgs& a, bool own, int64_t r, int6
     }
   }
   if (a.ldos) {
-#pragma unroll
-    for (int off = 1; off < L; off <<= 1) {
-      s1 += __shfl_xor(s1, off, kWave);
-      s2 += __shfl_xor(s2, off, kWave);
-    }
+    s1 = group_sum<L>(s1);
+    if (a.ldos_sq) s2 = group_sum<L>(s2);
     if (own && q == 0) {
       const int64_t t = static_cast<int64_t>(a.stage_pos) * a.n + r;
       a.stage[t] = s1 * a.inv_k;
