@@ -122,8 +122,8 @@ def cpu_baseline(workload: str, k: int, ldos: bool, seed: int):
         n, s, d = sg.barabasi_albert(1_000_000, 5, seed=seed, twin_pairs=25_000)
         sample = "same BA-1M graph and probe count, first 10 moments (9 products)"
     elif workload in ("rmat27", "rmat22"):
-        n, s, d = sg.rmat(21, 8, seed=seed)
-        sample = "R-MAT scale 21 ef 8 (same a,b,c,d), same probe count, first 10 moments (9 products)"
+        n, s, d = sg.rmat(22, 8, seed=seed)
+        sample = "R-MAT scale 22 ef 8 (same a,b,c,d), same probe count, first 10 moments (9 products)"
     else:
         n, s, d = sg.erdos_renyi(2000, 0.005, seed=seed)
         sample = "same ER-2000 graph and probe count, first 10 moments (9 products)"
