@@ -32,6 +32,12 @@
  *   - A graph handle keeps a workspace (probe blocks, recurrence state,
  *     partial sums) that grows on demand; calls that use the same graph
  *     handle must not overlap in time (on different streams or threads).
+ *   - Device memory the library allocates comes from a per-device cache:
+ *     memory released by nd_*_free (or by a workspace that grows) is kept
+ *     for reuse until the process ends, up to ND_POOL_BYTES (default 32 GiB)
+ *     of unused blocks; a block is handed out again only after the device has
+ *     finished all queued work, and the cache is emptied when an allocation
+ *     fails.  ND_ALLOC_LIMIT_BYTES caps the size of any single allocation.
  *   - Results are deterministic: the same (graph, seed, flags, sizes) give
  *     bit-identical outputs on the same device.  No floating-point atomics.
  *   - Node ids: the builder drops isolated nodes and renumbers the survivors
