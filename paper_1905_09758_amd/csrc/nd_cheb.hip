@@ -155,6 +155,7 @@ struct StepArgs {
                            // 3: Lanczos steps (per-probe scales, product with the current vector)
   uint64_t seed;           // probe seed and index of this block's first probe (zmode 1)
   int64_t j0;
+  const uint64_t* zbits;   // zmode 1: sign bits of the Rademacher probe row, bit j set for -1
   const int32_t* zcls;     // zmode 1 with twin filtering: class of each internal row or -1
   const void* zcls_val;    // [n_classes][kp] projected probe rows of the classes
   void* chunk_part;
@@ -235,6 +236,7 @@ struct RowOperands {
   T xp[16 / sizeof(T)];
   T z[ZM == 0 ? 16 / sizeof(T) : 1];
   T xo[kOwnRow<ZM> ? 16 / sizeof(T) : 1];
+  uint64_t zw;  // ZM == 1: the row's probe sign bits
   int64_t node;
 };
 
@@ -242,6 +244,7 @@ template <typename T, int ZM>
 __device__ inline void load_row_operands(const StepArgs& a, bool own, int64_t r, int q, RowOperands<T, ZM>& o) {
   constexpr int PPL = 16 / sizeof(T);
   o.node = 0;
+  o.zw = 0;
 #pragma unroll
   for (int c = 0; c < PPL; ++c) o.xp[c] = T(0);
   if constexpr (ZM == 0) {
@@ -255,15 +258,17 @@ __device__ inline void load_row_operands(const StepArgs& a, bool own, int64_t r,
   if (own) {
     if (!a.first) load16_nt<T>(reinterpret_cast<const T*>(a.xio) + r * a.kp + q * PPL, o.xp);
     if constexpr (!kOwnRow<ZM>) {
-      if (ZM == 1 || a.ldos || a.cv_g) o.node = a.perm[r];
+      if (a.cv_g) o.node = a.perm[r];
     }
+    if constexpr (ZM == 1) o.zw = a.zbits[r];
     if constexpr (ZM == 0) load16_nt<T>(reinterpret_cast<const T*>(a.z) + r * a.kp + q * PPL, o.z);
     if constexpr (kOwnRow<ZM>) load16<T>(reinterpret_cast<const T*>(a.xg) + r * a.kp + q * PPL, o.xo);
   }
 }
 
-// Probe values of row r for this lane: read (ZM == 0), or regenerated from
-// the counter-based generator, twin-class rows taken from the class table.
+// Probe values of row r for this lane: read (ZM == 0), or the Rademacher
+// signs of the row's sign word (ZM == 1; the word is loaded with the other
+// row operands), twin-class rows taken from the class table.
 template <typename T, int ZM>
 __device__ inline void row_probes(const StepArgs& a, bool own, int64_t r, int q, const RowOperands<T, ZM>& o,
                                   T (&z)[16 / sizeof(T)]) {
@@ -282,7 +287,7 @@ __device__ inline void row_probes(const StepArgs& a, bool own, int64_t r, int q,
 #pragma unroll
         for (int c = 0; c < PPL; ++c) {
           const int j = q * PPL + c;
-          if (j < a.k_batch) z[c] = static_cast<T>(rademacher_entry(a.seed, a.j0 + j, o.node));
+          if (j < a.k_batch) z[c] = ((o.zw >> j) & 1) ? T(-1) : T(1);
         }
       }
     }
@@ -688,6 +693,22 @@ __global__ void k_unit_probes(int k_batch, int ld, const int32_t* __restrict__ n
   X0[r * ld + j] = static_cast<T>(1.0 / sqrt(static_cast<double>(row_ptr[r + 1] - row_ptr[r])));
 }
 
+// Sign bits of a Rademacher probe block, one 64-bit word per internal row
+// (bit j set where probe j is -1; ld <= 64): the step kernels read these 8
+// bytes per row instead of regenerating the row's entries.  One wavefront per
+// row.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sign_bits(int64_t n, int ld, const T* __restrict__ Z,
+                                                      uint64_t* __restrict__ bits) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int64_t i = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
+    const bool neg = lane < ld && Z[i * ld + lane] < T(0);
+    const uint64_t w = __ballot(neg);
+    if (lane == 0) bits[i] = w;
+  }
+}
+
 // Twin projection Z <- P P^T Z (Sec. 3.4): each class's rows replaced by the
 // class mean (fp64 sum in member order).  Members of a class share their
 // neighbourhood and hence their degree.  Member node i lives in row inv[i]
@@ -1057,9 +1078,17 @@ nd_status setup_block(nd_graph* g, const MomentJob& job, int j0, int kb, hipStre
                        static_cast<int64_t>(j0), job.seed, job.gaussian ? 1 : 0, in->row_ptr, in->perm, Z, A);
   }
   ND_LAUNCH_CHECK();
-  // Rademacher rows are regenerated inside the step kernels (no probe-block
-  // reads); the projected rows of twin classes come from a small table
+  // Rademacher rows reach the step kernels as one sign word per row (no
+  // probe-block reads); the projected rows of twin classes come from a small
+  // table
   const int zmode = (!job.gaussian && !job.unit_nodes && !probe_buffer_forced()) ? 1 : 0;
+  uint64_t* zbits = nullptr;
+  if (zmode) {
+    ND_CHECK(g->ws_zbits.ensure(static_cast<size_t>(N) * sizeof(uint64_t)));
+    zbits = g->ws_zbits.as<uint64_t>();
+    hipLaunchKernelGGL(k_sign_bits<T>, dim3(grid_for(N, kWavesPerBlock)), dim3(kBlock), 0, st, N, kp, Z, zbits);
+    ND_LAUNCH_CHECK();
+  }
   const bool filt = job.motifs && job.motifs->n_classes > 0;
   int32_t* zcls = nullptr;
   T* zcls_val = nullptr;
@@ -1102,6 +1131,7 @@ nd_status setup_block(nd_graph* g, const MomentJob& job, int j0, int kb, hipStre
   a.zmode = zmode;
   a.seed = job.seed;
   a.j0 = j0;
+  a.zbits = zbits;
   a.zcls = zcls;
   a.zcls_val = zcls_val;
   a.chunk_part = g->ws_chunk.p;

@@ -172,7 +172,7 @@ struct nd_graph {
   float* dinv_sqrt = nullptr;  // [n]
   std::unique_ptr<nd::Internal> internal;              // built on first use
   std::map<int, std::unique_ptr<nd::Schedule>> sched;  // keyed by L
-  nd::Scratch ws_state, ws_partial, ws_chunk, ws_misc, ws_zcls, ws_stage;  // moment workspaces
+  nd::Scratch ws_state, ws_partial, ws_chunk, ws_misc, ws_zcls, ws_stage, ws_zbits;  // moment workspaces
   // ND_TIME_STEPS: HIP-event time of the sparse-product step launches of the
   // last moment call (the launches of moment 1 .. M-1 of every probe block)
   double step_ms = 0.0;
