@@ -937,13 +937,11 @@ int step_grid(int L) {
 }
 
 // ND_PROBE_BUFFER=1 makes the step kernels read the probe block instead of
-// regenerating Rademacher rows (tuning experiments).
+// the per-row sign words of Rademacher probes (read on every call: tuning
+// experiments, and tests that check both paths give identical results).
 bool probe_buffer_forced() {
-  static bool v = [] {
-    const char* e = std::getenv("ND_PROBE_BUFFER");
-    return e && std::atoi(e) == 1;
-  }();
-  return v;
+  const char* e = std::getenv("ND_PROBE_BUFFER");
+  return e && std::atoi(e) == 1;
 }
 
 // Probes per block of the recurrence (a power of two, at most 64);

@@ -399,6 +399,33 @@ def test_ldos_stage_grouping(case, nd, monkeypatch):
         assert o == outs[0]
 
 
+def test_sign_words_match_probe_rows(case, nd, monkeypatch):
+    """Rademacher probes reach the step kernels as one sign word per row; the
+    path that reads the probe block instead (ND_PROBE_BUFFER=1) must give
+    bit-identical global and per-node moments, twin filter on and off."""
+    import torch
+    name, _, g_or, g = case
+    k, M = 70, 37
+    m = nd.nd_motif_filter(g, seed=3)
+    outs = []
+    for forced in (None, "1"):
+        if forced is None:
+            monkeypatch.delenv("ND_PROBE_BUFFER", raising=False)
+        else:
+            monkeypatch.setenv("ND_PROBE_BUFFER", forced)
+        res = []
+        for motifs in (None, m):
+            ld = _zeros(g.n * M, torch.float64)
+            mu = _zeros(M, torch.float64)
+            nd.nd_ldos_moments(g, motifs, k, M, 9, 0, ld, mu=mu)
+            mu2 = _zeros(M, torch.float64)
+            nd.nd_cheb_moments(g, motifs, k, M, 9, 0, mu2)
+            res.append((ld.cpu().numpy().tobytes(), mu.cpu().numpy().tobytes(), mu2.cpu().numpy().tobytes()))
+        outs.append(res)
+    monkeypatch.delenv("ND_PROBE_BUFFER", raising=False)
+    assert outs[0] == outs[1]
+
+
 def test_control_variate_ldos(case, nd):
     import torch
     name, _, g_or, g = case
