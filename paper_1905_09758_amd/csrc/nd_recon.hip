@@ -79,18 +79,36 @@ __global__ __launch_bounds__(kBlock) void k_recon_gemm(const double* __restrict_
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int m0 = 0; m0 < M; m0 += kKC) {
+  // stage loads go through registers: the next stage's moments and table
+  // entries are in flight while the current stage is multiplied
+  constexpr int kPA = kTR * kKC / kBlock, kPB = kKC * kTC / kBlock;
+  static_assert(kPA * kBlock == kTR * kKC && kPB * kBlock == kKC * kTC, "stage tile / block size");
+  double ra[kPA], rb[kPB];
+  auto fetch = [&](int m0) {
     const int mm = M - m0 < kKC ? M - m0 : kKC;
-    __syncthreads();
-    for (int t = threadIdx.x; t < kTR * kKC; t += kBlock) {
-      const int r = t / kKC, k = t % kKC;
-      sa[r * kLdA + k] = (r0 + r < n_rows && k < mm) ? mu[(r0 + r) * M + m0 + k] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kPA; ++u) {
+      const int t = threadIdx.x + u * kBlock, r = t / kKC, k = t % kKC;
+      ra[u] = (r0 + r < n_rows && k < mm) ? mu[(r0 + r) * M + m0 + k] : 0.0;
     }
-    for (int t = threadIdx.x; t < kKC * kTC; t += kBlock) {
-      const int k = t / kTC, c = t % kTC;
-      sb[t] = Wt[static_cast<int64_t>(m0 + k) * cpad + c0 + c];
+#pragma unroll
+    for (int u = 0; u < kPB; ++u) {
+      const int t = threadIdx.x + u * kBlock, k = t / kTC, c = t % kTC;
+      rb[u] = Wt[static_cast<int64_t>(m0 + k) * cpad + c0 + c];
     }
+  };
+  fetch(0);
+  for (int m0 = 0; m0 < M; m0 += kKC) {
     __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPA; ++u) {
+      const int t = threadIdx.x + u * kBlock;
+      sa[(t / kKC) * kLdA + t % kKC] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kPB; ++u) sb[threadIdx.x + u * kBlock] = rb[u];
+    __syncthreads();
+    if (m0 + kKC < M) fetch(m0 + kKC);
 #pragma unroll 8
     for (int k = 0; k < kKC; ++k) {
       double x[4], y[4];
