@@ -242,6 +242,49 @@ def nested_study(args) -> dict:
     return out
 
 
+def motif_study(args) -> dict:
+    """How much of each graph's spectrum the motif filters remove, kind by
+    kind: classes, member nodes and removed eigenvalue mass (sum of
+    (|C| - 1) / N over the classes, the weight of the exact spikes), with the
+    detection time, on the benchmark graphs and the paper's model-verification
+    graphs."""
+    import torch
+    import paper_1905_09758_amd as nd
+    import synthgraph as sg
+    kinds = (("open twins", nd.ND_TWINS_OPEN), ("closed twins", nd.ND_TWINS_CLOSED),
+             ("pendant twins", nd.ND_PENDANTS), ("hub paths", nd.ND_HUBPATHS),
+             ("all", nd.ND_TWINS_OPEN | nd.ND_TWINS_CLOSED | nd.ND_PENDANTS | nd.ND_HUBPATHS))
+    graphs = (("BA n=1e6 m=5 + 25k planted twin pairs", lambda: sg.barabasi_albert(1_000_000, 5, seed=args.seed,
+                                                                                  twin_pairs=25_000)),
+              ("R-MAT scale 20 ef 8", lambda: sg.rmat(20, 8, seed=args.seed)),
+              ("R-MAT scale 22 ef 16", lambda: sg.rmat(22, 16, seed=args.seed)),
+              ("BA n=5000 m=1", lambda: sg.barabasi_albert(5000, 1, seed=args.seed)),
+              ("BA n=5000 m=5", lambda: sg.barabasi_albert(5000, 5, seed=args.seed)),
+              ("WS n=5000 5k edges p=0.5", lambda: sg.watts_strogatz(5000, 2, 0.5, seed=args.seed)),
+              ("WS n=5000 50k edges p=0.5", lambda: sg.watts_strogatz(5000, 20, 0.5, seed=args.seed)))
+    out = {"graphs": []}
+    for name, make in graphs:
+        n, s, d = make()
+        g = nd.nd_build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+        del s, d
+        row = {"graph": name, "n": g.n, "nnz": g.nnz, "kinds": {}}
+        for kname, kmask in kinds:
+            nd.nd_motif_filter(g, args.seed, kmask)          # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m = nd.nd_motif_filter(g, args.seed, kmask)
+            dt = time.perf_counter() - t0
+            mass = sum(w for _, w in m.spikes)
+            row["kinds"][kname] = {"classes": m.n_classes, "members": m.n_members,
+                                   "removed_mass": round(mass, 6), "distinct_spikes": len(m.spikes),
+                                   "detect_ms": round(dt * 1e3, 3)}
+            del m
+        out["graphs"].append(row)
+        del g
+        torch.cuda.empty_cache()
+    return out
+
+
 def cv_study(args) -> dict:
     """Learned control variate study: train on synthetic graphs of four
     families with LDOS targets from the method itself, then compare the
@@ -352,6 +395,9 @@ def main():
                          "the rate still counts the products actually done")
     ap.add_argument("--nested-study", action="store_true",
                     help="exact PDOS by nested dissection vs 64-probe KPM on a lattice and a tree")
+    ap.add_argument("--motif-study", action="store_true",
+                    help="removed spectral mass and detection time of each motif kind on the benchmark and "
+                         "model-verification graphs")
     ap.add_argument("--precision-study", action="store_true",
                     help="fp32 vs fp64 recurrence state on R-MAT scale 22 (32 probes, 1000 moments)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -386,6 +432,9 @@ def main():
         return
     if args.nested_study:
         print(json.dumps(nested_study(args)), flush=True)
+        return
+    if args.motif_study:
+        print(json.dumps(motif_study(args)), flush=True)
         return
     W = WORKLOADS[args.workload]
     k, M = W.probes, W.moments
