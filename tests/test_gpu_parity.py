@@ -245,6 +245,36 @@ def test_global_moments(case, nd, k, M):
     assert np.max(np.abs(mupp - mupp_o)) < TOL_MU
 
 
+@pytest.mark.parametrize("k,M", [(1, 1), (1, 2), (2, 3), (65, 2), (129, 4), (64, 33)])
+@pytest.mark.parametrize("state", ["fp32", "fp64"])
+def test_edge_sizes(case, nd, k, M, state):
+    """Degenerate and boundary sizes: one moment (no sparse step), one step,
+    one probe (three padding lanes), a last probe block of one probe, three
+    probe blocks, and one more moment than an LDOS staging block holds;
+    global, per-probe and per-node moments against the oracle."""
+    import torch
+    name, _, g_or, g = case
+    flags = nd.ND_STATE_FP64 if state == "fp64" else 0
+    H = og.normalized_adjacency(g_or)
+    Z = orng.rademacher(g_or.n, k, 13)
+    mu_o, mupp_o, C_o = kpm.stochastic_moments(H, Z, M)
+    mu = _zeros(M, torch.float64)
+    mupp = _zeros(k * M, torch.float64)
+    nd.nd_cheb_moments(g, None, k, M, 13, flags | nd.ND_TIME_STEPS, mu, mupp)
+    assert nd.nd_graph_step_timing(g)[1] == (M - 1) * ((k + 63) // 64)
+    tol_mu = TOL_FP64 if state == "fp64" else TOL_MU
+    tol_ld = TOL_FP64 if state == "fp64" else ldos_tol(M, name)
+    assert np.max(np.abs(mu.cpu().numpy() - mu_o)) < tol_mu
+    assert np.max(np.abs(mupp.cpu().numpy().reshape(k, M) - mupp_o)) < tol_mu
+    ld = _zeros(g.n * M, torch.float64)
+    mu2 = _zeros(M, torch.float64)
+    nd.nd_ldos_moments(g, None, k, M, 13, flags, ld, mu=mu2)
+    C = ld.cpu().numpy().reshape(g.n, M)
+    assert np.all(C[:, 0] == 1.0)
+    assert np.max(np.abs(C - C_o)) < tol_ld
+    assert np.max(np.abs(mu2.cpu().numpy() - mu_o)) < tol_mu
+
+
 @pytest.mark.parametrize("k,M", [(20, 100), (64, 61), (3, 200), (100, 30), (5, 1), (5, 2), (5, 3)])
 def test_global_moments_doubling(case, nd, k, M):
     """ND_MOMENT_DOUBLING: the same estimates from floor(M/2) products."""
