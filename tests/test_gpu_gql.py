@@ -100,14 +100,15 @@ def test_gql_filtered_and_gaussian(nd):
     _, mu_s, _, _ = twins.filtered_moments(H, Z, 2 * K, cls, ldos=False,
                                            lambdas=[twins.class_eigenvalue(g_or, c) for c in cls])
     assert np.max(np.abs(gql.gql_moments(rules, 2 * K) - mu_s)) < 1e-9
-    # Gaussian probes: the GPU's fp32 probe values feed the oracle
-    Zd = torch.zeros(g.n * k, dtype=torch.float32, device="cuda")
-    nd.nd_make_probes(g, None, k, 9, nd.ND_PROBE_GAUSSIAN, Zd)
-    Zg = Zd.cpu().numpy().reshape(g.n, k).astype(np.float64)
+    # Gaussian probes from the oracle's own generator.  Its libm may differ
+    # from the device's by an ulp before the fp32 rounding (a probe entry
+    # then differs by <= 4e-7 relative), which moves a moment by at most
+    # ~2 * 4e-7 * max|z| * rms(z) ~ 1e-5; equal entries leave it exact.
+    Zg = orng.gaussian(g_or.n, k, 9)
     nodes, weights, steps, _, _ = _run(nd, g, None, k, K, 9, nd.ND_PROBE_GAUSSIAN | nd.ND_STATE_FP64)
     rules = _rules(nodes, weights, steps, k, K)
     mu_g, _, _ = kpm.stochastic_moments(H, Zg, 2 * K, ldos=False)
-    assert np.max(np.abs(gql.gql_moments(rules, 2 * K) - mu_g)) < 1e-9
+    assert np.max(np.abs(gql.gql_moments(rules, 2 * K) - mu_g)) < 1e-5
 
 
 def test_gql_errors(nd):
