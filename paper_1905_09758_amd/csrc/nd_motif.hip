@@ -55,28 +55,93 @@ __device__ inline int64_t pendant_leaf(const int64_t* row_ptr, const int32_t* co
 // Hash modes: 0 open neighbourhood, 1 closed, 2 the neighbourhood without
 // the private leaf (pendant-twin candidates; other nodes get distinct keys
 // with the top bit set, which the verification never groups).
+//
+// A wavefront takes 64 consecutive nodes: each lane hashes its own node when
+// it has at most kLongRow neighbours; the longer rows of the 64 are then
+// hashed by the whole wavefront in turn (lanes stride over the neighbours).
+// The hash is a sum mod 2^64, so the split does not change its value.
+constexpr int64_t kLongRow = 32;
+
+__device__ inline uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const uint32_t lo = __shfl_xor(static_cast<uint32_t>(x), off, kWave);
+    const uint32_t hi = __shfl_xor(static_cast<uint32_t>(x >> 32), off, kWave);
+    x += (static_cast<uint64_t>(hi) << 32) | lo;
+  }
+  return x;
+}
+
 __global__ __launch_bounds__(kBlock) void k_twin_hash(const int64_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ col, int64_t n, uint64_t key,
                                                       uint64_t mask, int mode, uint64_t* __restrict__ h,
                                                       uint32_t* __restrict__ idx) {
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    idx[i] = static_cast<uint32_t>(i);
-    if (mode == 2) {
-      const int64_t leaf = pendant_leaf(row_ptr, col, i);
-      if (leaf < 0) {
-        h[i] = (uint64_t(1) << 63) | static_cast<uint64_t>(i);
-        continue;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t n_waves = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
+  for (int64_t base = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kWave * kWave; base < n;
+       base += n_waves * kWave) {
+    const int64_t i = base + lane;
+    bool is_long = false;
+    if (i < n) {
+      idx[i] = static_cast<uint32_t>(i);
+      is_long = row_ptr[i + 1] - row_ptr[i] > kLongRow;
+      if (!is_long) {
+        if (mode == 2) {
+          const int64_t leaf = pendant_leaf(row_ptr, col, i);
+          if (leaf < 0) {
+            h[i] = (uint64_t(1) << 63) | static_cast<uint64_t>(i);
+          } else {
+            uint64_t s = 0;
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+              if (col[e] != leaf) s += splitmix64(key, static_cast<uint64_t>(col[e]) + 1);
+            h[i] = (s & mask) & ~(uint64_t(1) << 63);
+          }
+        } else {
+          uint64_t s = mode == 1 ? splitmix64(key, static_cast<uint64_t>(i) + 1) : 0;
+          for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) s += splitmix64(key, static_cast<uint64_t>(col[e]) + 1);
+          h[i] = s & mask;
+        }
+      }
+    }
+    uint64_t longs = __ballot(is_long);
+    while (longs) {
+      const int l = __ffsll(static_cast<long long>(longs)) - 1;
+      longs &= longs - 1;
+      const int64_t b = base + l;
+      const int64_t e0 = row_ptr[b], e1 = row_ptr[b + 1];
+      int64_t leaf = -1;
+      bool keyed = true;
+      if (mode == 2) {
+        // the private leaf: the unique neighbour of degree 1, if exactly one
+        // (the scan stops at the second one, like pendant_leaf)
+        uint64_t cnt = 0, lsum = 0;
+        for (int64_t e = e0; e < e1 && cnt < 2; e += kWave) {
+          uint64_t c = 0, ls = 0;
+          if (e + lane < e1) {
+            const int32_t u = col[e + lane];
+            if (row_ptr[u + 1] - row_ptr[u] == 1) {
+              c = 1;
+              ls = static_cast<uint64_t>(u) + 1;
+            }
+          }
+          cnt += wave_sum_u64(c);
+          lsum += wave_sum_u64(ls);
+        }
+        keyed = cnt == 1;
+        leaf = keyed ? static_cast<int64_t>(lsum) - 1 : -1;
       }
       uint64_t s = 0;
-      for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
-        if (col[e] != leaf) s += splitmix64(key, static_cast<uint64_t>(col[e]) + 1);
-      h[i] = (s & mask) & ~(uint64_t(1) << 63);
-      continue;
+      if (keyed)
+        for (int64_t e = e0 + lane; e < e1; e += kWave)
+          if (col[e] != leaf) s += splitmix64(key, static_cast<uint64_t>(col[e]) + 1);
+      s = wave_sum_u64(s);
+      if (lane == 0) {
+        if (mode == 2)
+          h[b] = keyed ? ((s & mask) & ~(uint64_t(1) << 63)) : ((uint64_t(1) << 63) | static_cast<uint64_t>(b));
+        else
+          h[b] = ((mode == 1 ? splitmix64(key, static_cast<uint64_t>(b) + 1) : 0) + s) & mask;
+      }
     }
-    uint64_t s = mode == 1 ? splitmix64(key, static_cast<uint64_t>(i) + 1) : 0;
-    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) s += splitmix64(key, static_cast<uint64_t>(col[e]) + 1);
-    h[i] = s & mask;
   }
 }
 

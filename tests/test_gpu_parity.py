@@ -113,7 +113,45 @@ TWIN_GRAPHS = {
     "ba_m1": lambda: sg.barabasi_albert(3000, 1, seed=4),   # a tree: many pendant twins
     "pendants": lambda: _pendant_graph(5),
     "hubpaths": lambda: _hub_path_graph(6),
+    "long_rows": lambda: _long_row_graph(7),
 }
+
+
+def _long_row_graph(seed):
+    """Twins of every kind on rows longer than 64 neighbours (hashed by a whole
+    wavefront): three open twins on 80 core nodes, two closed twins on 70,
+    two pendant twins on 90 core nodes plus a private leaf each, a hub of
+    degree 100 with one leaf and no twin, and one with two leaves."""
+    n0, s, d = sg.erdos_renyi(300, 0.02, seed=seed)
+    rng = np.random.default_rng(seed)
+    ss, dd, nxt = list(s), list(d), n0
+
+    def join(v, nodes):
+        ss.extend([v] * len(nodes))
+        dd.extend(int(x) for x in nodes)
+
+    core = rng.choice(n0, 80, replace=False)
+    for _ in range(3):
+        join(nxt, core)
+        nxt += 1
+    core = rng.choice(n0, 70, replace=False)
+    join(nxt, core)
+    join(nxt + 1, core)
+    ss.append(nxt)
+    dd.append(nxt + 1)
+    nxt += 2
+    core = rng.choice(n0, 90, replace=False)
+    for _ in range(2):
+        join(nxt, core)
+        join(nxt, [nxt + 1])
+        nxt += 2
+    join(nxt, rng.choice(n0, 99, replace=False))
+    join(nxt, [nxt + 1])
+    nxt += 2
+    join(nxt, rng.choice(n0, 98, replace=False))
+    join(nxt, [nxt + 1, nxt + 2])
+    nxt += 3
+    return nxt, np.array(ss, np.int32), np.array(dd, np.int32)
 
 
 def _hub_path_graph(seed):
@@ -180,6 +218,9 @@ def test_twin_kinds_bit_exact(nd, gname, kind):
         assert 0.0 in sig and -0.5 in sig and -1.0 / 3.0 in sig and -0.25 in sig
     if gname in ("ba_m1", "pendants") and kind in ("pendants", "all"):
         assert any(isinstance(x, list) for x in sig)
+    if gname == "long_rows":
+        want = {"open": 1, "closed": 1, "both": 2, "pendants": 1, "all": 3, "hubpaths": 0}[kind]
+        assert len([c for c in cls if g_or.deg[c[0]] > 64]) == want
     if gname in ("pendants", "hubpaths") and kind == "all":
         lams = {l for l, _ in m.spikes}
         assert {0.5, -0.5} <= lams
