@@ -351,7 +351,8 @@ nd_status build_impl(int64_t n_nodes, int64_t m, const int32_t* src_in, const in
       hipLaunchKernelGGL(k_rows_cols, dim3(grid_for(nnz, kBlock)), dim3(kBlock), 0, st, alt, nnz, bits,
                          new_id, g->row_ptr, g->col, n);
       ND_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_dinv, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, g->row_ptr, n, g->dinv_sqrt,
+      // a grid-stride grid of 256 blocks: one max-degree atomic per wavefront
+      hipLaunchKernelGGL(k_dinv, dim3(grid_for(n, kBlock, 256)), dim3(kBlock), 0, st, g->row_ptr, n, g->dinv_sqrt,
                          counters + 2);
       ND_LAUNCH_CHECK();
       unsigned long long mx = 0;

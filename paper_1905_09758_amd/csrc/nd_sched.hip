@@ -68,9 +68,12 @@ __device__ inline int ceil_log2_dev(int64_t x) {
 }
 
 // cnt[b] = rows with log2 P = b (b <= log2_pmax); cnt[log2_pmax + 1] = split rows.
+// Each wavefront counts in registers over its grid-stride rows and adds its
+// totals once at the end (the grid is a few hundred blocks).
 __global__ __launch_bounds__(kBlock) void k_bin_count(const int64_t* __restrict__ row_ptr, int64_t n, int log2_pmax,
                                                       int64_t chunk_nnz, int slot_nnz,
                                                       unsigned long long* __restrict__ cnt) {
+  unsigned long long wc[kMaxBins + 2] = {};
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock; base < n;
        base += static_cast<int64_t>(gridDim.x) * kBlock) {
     const int64_t i = base + threadIdx.x;
@@ -84,10 +87,14 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int64_t* __restrict_
         if (b > log2_pmax) b = log2_pmax;
       }
     }
-    for (int t = 0; t <= log2_pmax + 1; ++t) {
-      const unsigned long long c = __popcll(__ballot(b == t));
-      if ((threadIdx.x & (kWave - 1)) == 0 && c) atomicAdd(&cnt[t], c);
-    }
+#pragma unroll
+    for (int t = 0; t < kMaxBins + 2; ++t)
+      if (t <= log2_pmax + 1) wc[t] += __popcll(__ballot(b == t));
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+    for (int t = 0; t < kMaxBins + 2; ++t)
+      if (t <= log2_pmax + 1 && wc[t]) atomicAdd(&cnt[t], wc[t]);
   }
 }
 
@@ -173,7 +180,7 @@ nd_status get_schedule(nd_graph* g, int L, hipStream_t st, Schedule** out) {
     unsigned long long* dcnt;
     ND_CHECK(t.get(&dcnt, kMaxBins + 1));
     ND_HIP(hipMemsetAsync(dcnt, 0, sizeof(cnt), st));
-    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, in->row_ptr, n, log2_pmax,
+    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(n, kBlock, 256)), dim3(kBlock), 0, st, in->row_ptr, n, log2_pmax,
                        s->chunk_nnz, s->slot_nnz, dcnt);
     ND_LAUNCH_CHECK();
     ND_HIP(hipMemcpyAsync(cnt, dcnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
