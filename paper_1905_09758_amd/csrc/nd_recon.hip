@@ -21,6 +21,8 @@ __device__ inline double jackson_g(int m, int M) {
 }
 
 // Column tiles of the product: kTC columns, kKC moments per LDS stage.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 constexpr int kTR = 64;  // rows per block
 constexpr int kTC = 64;  // columns per launch
 constexpr int kKC = 32;  // moments per stage
@@ -56,9 +58,12 @@ __global__ __launch_bounds__(kBlock) void k_recon_table(int M, int Mp, int kerne
 }
 
 // out[row][c] = sum_m mu[row][m] Wt[m][c0 + c] - corr[c0 + c], c < ncols, for
-// one tile of kTC table columns: a block owns kTR rows, stages kKC moments of its rows and of
-// the column tile in LDS, and each thread accumulates a 4x4 register tile
-// (rows ty + 16 i, columns tx + 16 j) in a fixed order over m.
+// one tile of kTC table columns: a block owns kTR rows and stages kKC moments
+// of its rows and of the column tile in LDS; each wavefront multiplies a
+// 32 x 32 quarter of the tile on the fp64 matrix cores, four
+// v_mfma_f64_16x16x4f64 per 4 moments.  Their operand layout (checked on the
+// device): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16], and element
+// i of its result is D[4 i + l / 16][l % 16].
 // With `hist` set, the tile holds all n_bins + 1 edge columns and the block
 // writes the bin masses hist[row][b] = (F_b - F_{b+1}) / pi + spikes directly.
 __global__ __launch_bounds__(kBlock) void k_recon_gemm(const double* __restrict__ mu, int64_t n_rows, int M,
@@ -72,13 +77,15 @@ __global__ __launch_bounds__(kBlock) void k_recon_gemm(const double* __restrict_
   static_assert(kTR * (kTC + 1) >= kTR * kLdA + kKC * kTC, "LDS tile too small");
   double* sa = lds;                // [kTR][kLdA]
   double* sb = lds + kTR * kLdA;   // [kKC][kTC]
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;  // the wavefront's quarter of the tile
+  const int lr = lane % 16, lk = lane / 16;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kTR;
-  double acc[4][4];
+  v4d acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
   // stage loads go through registers: the next stage's moments and table
   // entries are in flight while the current stage is multiplied
   constexpr int kPA = kTR * kKC / kBlock, kPB = kKC * kTC / kBlock;
@@ -109,41 +116,44 @@ __global__ __launch_bounds__(kBlock) void k_recon_gemm(const double* __restrict_
     for (int u = 0; u < kPB; ++u) sb[threadIdx.x + u * kBlock] = rb[u];
     __syncthreads();
     if (m0 + kKC < M) fetch(m0 + kKC);
-#pragma unroll 8
-    for (int k = 0; k < kKC; ++k) {
-      double x[4], y[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) x[i] = sa[(ty + 16 * i) * kLdA + k];
+    for (int k0 = 0; k0 < kKC; k0 += 4) {
+      double x[2], y[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) y[j] = sb[k * kTC + tx + 16 * j];
+      for (int t = 0; t < 2; ++t) x[t] = sa[(wr + 16 * t + lr) * kLdA + k0 + lk];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int t = 0; t < 2; ++t) y[t] = sb[(k0 + lk) * kTC + wc + 16 * t + lr];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(x[i], y[j], acc[i][j]);
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i], y[j], acc[i][j], 0, 0, 0);
     }
   }
   if (!hist) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t r = r0 + ty + 16 * i;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c = tx + 16 * j;
-        if (r < n_rows && c < ncols) out[r * ld_out + c] = corr ? acc[i][j] - corr[c0 + c] : acc[i][j];
-      }
-    }
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t r = r0 + wr + 16 * i + 4 * e + lk;
+          const int c = wc + 16 * j + lr;
+          if (r < n_rows && c < ncols) out[r * ld_out + c] = corr ? acc[i][j][e] - corr[c0 + c] : acc[i][j][e];
+        }
     return;
   }
   // fused bins: F tile through LDS, then the differences of adjacent edges
   constexpr int kLdF = kTC + 1;
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = tx + 16 * j;
-      lds[(ty + 16 * i) * kLdF + c] = corr && c < ncols ? acc[i][j] - corr[c] : acc[i][j];
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr + 16 * i + 4 * e + lk, c = wc + 16 * j + lr;
+        lds[r * kLdF + c] = corr && c < ncols ? acc[i][j][e] - corr[c] : acc[i][j][e];
+      }
   __syncthreads();
   const int nb = ncols - 1;
   for (int t = threadIdx.x; t < kTR * nb; t += kBlock) {
