@@ -61,8 +61,8 @@ __global__ __launch_bounds__(kBlock) void k_recon_table(int M, int Mp, int kerne
 // one tile of kTC table columns: a block owns kTR rows and stages kKC moments
 // of its rows and of the column tile in LDS; each wavefront multiplies a
 // 32 x 32 quarter of the tile on the fp64 matrix cores, four
-// v_mfma_f64_16x16x4f64 per 4 moments.  Their operand layout (checked on the
-// device): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16], and element
+// v_mfma_f64_16x16x4f64 per 4 moments.  Their operand layout (any other
+// reading fails the reconstruction parity tests): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16], and element
 // i of its result is D[4 i + l / 16][l % 16].
 // With `hist` set, the tile holds all n_bins + 1 edge columns and the block
 // writes the bin masses hist[row][b] = (F_b - F_{b+1}) / pi + spikes directly.
