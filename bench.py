@@ -13,10 +13,14 @@ list is already resident in HBM:
 The figure of merit is G(nnz*probe*moment)/s = nnz * probes * (M-1) / step
 time.  The roofline object reports the sparse step kernel (the dominant
 kernel): algorithmic bytes per launch (compulsory traffic of one step: the
-int32 pattern, row pointers, the degree scale, one read of X_m, one read of
-X_{m-1}, one write of X_{m+1}, plus the per-node moment column when LDOS is
-computed) divided by its average launch time from HIP events on the launch
-stream, against the 8 TB/s HBM3E peak.
+int32 pattern, row pointers, the probe sign word of each row, one read of
+X_m, one read of X_{m-1}, one write of X_{m+1}, plus the twin-class index of
+each row when filtering and the per-node moment column when LDOS is computed)
+divided by its average launch time from HIP events on the launch stream,
+against the 8 TB/s HBM3E peak.
+
+With no flags it times the billion-edge workload: R-MAT scale 27, 16 probes,
+200 moments, global DOS.
 
 The CPU baseline times the fp64 oracle (plain numpy/scipy, one thread) on a
 bounded sample, following the paper's timing protocol (the first 10 moments).
@@ -40,11 +44,19 @@ UNIT = "G(nnz·probe·moment)/s"
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(n: int, nnz: int, k: int, ldos: bool, state_bytes: int = 4, own_row: bool = False) -> int:
-    """Compulsory HBM traffic of one sparse step (one kernel launch); the
-    doubling and Lanczos steps also read each row's own entry of the gathered
-    block (own_row)."""
-    b = 4 * nnz + 8 * (n + 1) + 4 * n + (4 if own_row else 3) * state_bytes * k * n
+def algorithmic_bytes(n: int, nnz: int, k: int, ldos: bool, state_bytes: int = 4, own_row: bool = False,
+                      filtered: bool = False) -> int:
+    """Compulsory HBM traffic of one sparse step (one kernel launch) with
+    Rademacher probes: the int32 pattern, the row pointers, one 64-bit probe
+    sign word per row, one read of X_m, one read of X_{m-1}, one write of
+    X_{m+1}; plus the int32 twin-class index of every row when filtering and
+    the per-node moment column with LDOS.  The doubling and Lanczos steps also
+    read each row's own entry of the gathered block (own_row) and no signs."""
+    b = 4 * nnz + 8 * (n + 1) + (4 if own_row else 3) * state_bytes * k * n
+    if not own_row:
+        b += 8 * n
+        if filtered:
+            b += 4 * n
     if ldos:
         b += 8 * n
     return b
@@ -122,8 +134,12 @@ def cpu_baseline(workload: str, k: int, ldos: bool, seed: int):
         n, s, d = sg.barabasi_albert(1_000_000, 5, seed=seed, twin_pairs=25_000)
         sample = "same BA-1M graph and probe count, first 10 moments (9 products)"
     elif workload in ("rmat27", "rmat22"):
+        # the scale-27 graph itself needs ~50 GB and minutes in the oracle's
+        # graph build, so a smaller R-MAT of the same parameters stands in
         n, s, d = sg.rmat(22, 8, seed=seed)
-        sample = "R-MAT scale 22 ef 8 (same a,b,c,d), same probe count, first 10 moments (9 products)"
+        sample = ("stand-in graph, not the timed one: R-MAT scale 22 ef 8 (same a,b,c,d; the timed graph "
+                  "does not fit the oracle's graph build in the sample's time), same probe count, first 10 "
+                  "moments (9 products)")
     else:
         n, s, d = sg.erdos_renyi(2000, 0.005, seed=seed)
         sample = "same ER-2000 graph and probe count, first 10 moments (9 products)"
@@ -379,7 +395,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ba1m_twins", choices=["ba1m_twins", "rmat27", "rmat22", "er2000", "cv5"])
+    ap.add_argument("--workload", default="rmat27", choices=["ba1m_twins", "rmat27", "rmat22", "er2000", "cv5"])
     ap.add_argument("--cv-train", type=int, default=200, help="cv5: training graphs")
     ap.add_argument("--cv-held", type=int, default=20, help="cv5: held-out graphs")
     ap.add_argument("--cv-nmin", type=int, default=10_000)
@@ -507,7 +523,8 @@ def main():
     work = nnz * k * products
     value = work / (ms_step * 1e-3) / 1e9
     avg_launch_ms = kern_ms / max(kern_n, 1)
-    b_launch = algorithmic_bytes(n, nnz, k, W.ldos, own_row=bool(not W.ldos and (args.doubling or args.gql)))
+    b_launch = algorithmic_bytes(n, nnz, k, W.ldos, own_row=bool(not W.ldos and (args.doubling or args.gql)),
+                                 filtered=use_filter)
     achieved = b_launch / (avg_launch_ms * 1e-3) / 1e9
     # the counter records are of the plain Chebyshev step launches
     traffic = profiled_traffic(args.workload) if not (args.doubling or args.gql) else None
@@ -535,7 +552,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_GBs": round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1) if traffic else None,
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
+                     "traffic_unit": "L2-miss (fabric) bytes per launch, rocprofv3 FETCH_SIZE x 2.0 + "
+                                     "WRITE_SIZE x 1.0: requests leaving the L2, Infinity Cache hits "
+                                     "included, so not DRAM bytes",
                      "kernel": "k_cheb_step", "avg_launch_ms": round(avg_launch_ms, 5),
                      "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                      "algorithmic_bytes_per_launch": b_launch},

@@ -227,13 +227,42 @@ nd_status nd_cheb_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
                           int32_t n_moments, uint64_t probe_seed, uint32_t flags, double* mu,
                           double* mu_pp, void* stream);
 
+/* nd_cheb_moments without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as nd_cheb_moments
+ * (bit-identical), without motif filtering and without ND_TIME_STEPS.
+ * Every buffer the kernels need besides the inputs and outputs (recurrence
+ * state, probe sign words, moment partials, and the per-probe moments when
+ * mu_pp is NULL) lives in one fixed device workspace of 64 MiB that the
+ * library holds on each GPU it runs on until the process ends; the
+ * recurrence state alone takes 3 x N x padded probes x 4 bytes (8 with
+ * ND_STATE_FP64), so this serves graphs up to roughly 340k nodes at 16
+ * probes or 85k nodes at 64.
+ * Preconditions: an earlier allocating call (nd_cheb_moments or
+ * nd_ldos_moments) with the same probe count has run on this graph (it
+ * builds the graph's row schedule, which this call only reads).
+ * Calls on one GPU share its workspace and leave their data in it: calls
+ * that overlap in time on one GPU (different streams, or host threads)
+ * race and must be serialised by the caller.  Nothing in the workspace needs
+ * to start at zero (every buffer is written before it is read).
+ * Errors: ND_EINVAL for a workspace need above 64 MiB (message states the
+ * need), a graph without a schedule for this probe count, ND_TIME_STEPS,
+ * or any argument error of nd_cheb_moments; no call fails for lack of
+ * memory. */
+nd_status nd_cheb_moments_noalloc(const nd_graph* g, int32_t n_probes, int32_t n_moments,
+                                  uint64_t probe_seed, uint32_t flags, double* mu, double* mu_pp,
+                                  void* stream);
+
 /* Per-node LDOS / PDOS moments (Sec. 3.1, eqn pdoscoeff with eq. probe_diag):
  *   ldos[i][m] = (1/k) sum_j v_ijm,   v_ijm = z_ij (T_m(H) z_j)_i,
  * row-major [N][n_moments] (the matrix C of the paper's Algorithm 1 output).
  *   cv_g     NULL, or device float [N][n_moments]: a diagonal control variate
  *            g; then v_ijm = g_im + z_ij ((T_m(H) - diag g_m) z_j)_i, which
  *            is unbiased for any g (with +/-1 probes it equals the plain
- *            estimate exactly).
+ *            estimate exactly).  Not combined with motif filtering: the
+ *            projected probe of a class member has E[z~_i^2] = 1/|C|, so
+ *            g (1 - z~_i^2) would bias that row.  A cv_g together with
+ *            motifs that hold classes is rejected with ND_EINVAL.
  *   motifs   NULL, or twin classes: probes projected as in nd_cheb_moments,
  *            and each class member i gets the removed part back exactly,
  *            ldos[i][m] += (1 - 1/|C|) T_m(lambda_C) (the mean of T_m(+-lambda_C)
@@ -247,7 +276,8 @@ nd_status nd_cheb_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
  * up to 32 launches' LDOS terms (8 bytes per node and launch, twice with
  * ldos_sq, at most 1 GiB); the output rows are written 32 moments at a time.
  * Errors: ND_EINVAL for NULL ldos, a graph without nodes, foreign motifs,
- * unknown flags or ND_MOMENT_DOUBLING (global moments only); ND_ENOMEM when
+ * cv_g with twin classes, unknown flags or ND_MOMENT_DOUBLING (global
+ * moments only); ND_ENOMEM when
  * the workspace cannot be allocated. */
 nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes,
                           int32_t n_moments, uint64_t probe_seed, uint32_t flags,

@@ -39,7 +39,7 @@ EXPORTS = (
     "nd_graph_free",
     "nd_motif_filter", "nd_motif_info", "nd_motif_export", "nd_motif_export_lambda", "nd_motifs_free",
     "nd_make_probes",
-    "nd_cheb_moments", "nd_ldos_moments", "nd_pdos_nodes", "nd_pdos_nested", "nd_gql", "nd_gql_pdos", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_column_stats",
+    "nd_cheb_moments", "nd_cheb_moments_noalloc", "nd_ldos_moments", "nd_pdos_nodes", "nd_pdos_nested", "nd_gql", "nd_gql_pdos", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_column_stats",
     "nd_mlp_forward", "nd_mlp_grad", "nd_adam_step", "nd_last_error",
 )
 
@@ -83,6 +83,7 @@ _sig("nd_motif_export_lambda", [_vp, _vp, _vp])
 _sig("nd_motifs_free", [_vp], None)
 _sig("nd_make_probes", [_vp, _vp, _i32, _u64, _u32, _vp, _vp])
 _sig("nd_cheb_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp])
+_sig("nd_cheb_moments_noalloc", [_vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp])
 _sig("nd_ldos_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp, _vp])
 _sig("nd_pdos_nodes", [_vp, _vp, _i32, _i32, _u32, _vp, _vp])
 _sig("nd_pdos_nested", [_vp, _i32, _i32, _i64, _u32, _vp, _vp, _vp])
@@ -276,6 +277,16 @@ def nd_cheb_moments(g: Graph, motifs, n_probes: int, n_moments: int, seed: int, 
     pp = _dev(mu_pp, torch.float64, n_probes * n_moments, "mu_pp")
     _check(_lib.nd_cheb_moments(g.handle, _h(motifs), n_probes, n_moments, seed, flags, pm, pp, _stream(stream)),
            "nd_cheb_moments")
+
+
+def nd_cheb_moments_noalloc(g: Graph, n_probes: int, n_moments: int, seed: int, flags: int, mu, mu_pp=None,
+                            stream=None):
+    """nd_cheb_moments on the library's fixed device workspace (no allocation)."""
+    import torch
+    pm = _dev(mu, torch.float64, n_moments, "mu")
+    pp = _dev(mu_pp, torch.float64, n_probes * n_moments, "mu_pp")
+    _check(_lib.nd_cheb_moments_noalloc(g.handle, n_probes, n_moments, seed, flags, pm, pp, _stream(stream)),
+           "nd_cheb_moments_noalloc")
 
 
 def nd_ldos_moments(g: Graph, motifs, n_probes: int, n_moments: int, seed: int, flags: int, ldos,

@@ -16,6 +16,7 @@
 // X_{m+1} overwrites X_{m-1} in place: row i reads only its own old row.
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 #include <vector>
 
 #include "nd_common.h"
@@ -972,7 +973,32 @@ int ldos_stage_launches(int64_t bytes_per_launch, int launches) {
   return S > launches ? launches : S;
 }
 
+// Device memory of one moment call: each buffer is the graph's growable
+// workspace of that name, or -- for the allocation-free entry point -- the
+// next 256-byte-aligned slice of a fixed arena (no allocation at all).
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+
+nd_status take(Arena* ar, Scratch& s, size_t bytes, void** out) {
+  if (!ar) {
+    ND_CHECK(s.ensure(bytes));
+    *out = s.p;
+    return ND_OK;
+  }
+  const size_t off = (ar->used + 255) & ~size_t(255);
+  if (off > ar->cap || bytes > ar->cap - off) {
+    set_error("internal: the fixed workspace is %zu bytes short", off + bytes - ar->cap);
+    return ND_EINVAL;
+  }
+  *out = ar->base + off;
+  ar->used = off + bytes;
+  return ND_OK;
+}
+
 struct MomentJob {
+  Arena* arena = nullptr;  // fixed device workspace instead of the graph's buffers
   const nd_motifs* motifs = nullptr;
   int k = 0, M = 0;
   uint64_t seed = 0;
@@ -1055,12 +1081,25 @@ nd_status setup_block(nd_graph* g, const MomentJob& job, int j0, int kb, hipStre
   const int kp = pow2_at_least(kb < PPL ? PPL : kb);
   const int L = kp * static_cast<int>(sizeof(T)) / 16;
   Schedule* sc = nullptr;
-  ND_CHECK(get_schedule(g, L, st, &sc));
+  if (job.arena) {
+    // the allocation-free path only uses a schedule an earlier call built
+    auto it = g->sched.find(L);
+    if (it == g->sched.end() || !g->internal) {
+      set_error("the graph has no row schedule for blocks of %d probes yet: run nd_cheb_moments once on it "
+                "with the same probe count first", kp);
+      return ND_EINVAL;
+    }
+    sc = it->second.get();
+  } else {
+    ND_CHECK(get_schedule(g, L, st, &sc));
+  }
   Internal* in = g->internal.get();
   const size_t blk = static_cast<size_t>(N) * kp * sizeof(T);
-  ND_CHECK(g->ws_state.ensure(3 * blk));
-  ND_CHECK(g->ws_chunk.ensure(static_cast<size_t>(sc->n_chunks > 0 ? sc->n_chunks : 1) * kp * sizeof(double)));
-  T* Z = g->ws_state.as<T>();
+  void *p_state = nullptr, *p_chunk = nullptr;
+  ND_CHECK(take(job.arena, g->ws_state, 3 * blk, &p_state));
+  ND_CHECK(take(job.arena, g->ws_chunk, static_cast<size_t>(sc->n_chunks > 0 ? sc->n_chunks : 1) * kp * sizeof(double),
+                &p_chunk));
+  T* Z = static_cast<T*>(p_state);
   T* A = Z + static_cast<int64_t>(N) * kp;
   T* B = A + static_cast<int64_t>(N) * kp;
   const int grid = grid_for(sc->n_items > 0 ? sc->n_items : 1, kWavesPerBlock, step_grid<T>(L));
@@ -1082,8 +1121,9 @@ nd_status setup_block(nd_graph* g, const MomentJob& job, int j0, int kb, hipStre
   const int zmode = (!job.gaussian && !job.unit_nodes && !probe_buffer_forced()) ? 1 : 0;
   uint64_t* zbits = nullptr;
   if (zmode) {
-    ND_CHECK(g->ws_zbits.ensure(static_cast<size_t>(N) * sizeof(uint64_t)));
-    zbits = g->ws_zbits.as<uint64_t>();
+    void* p = nullptr;
+    ND_CHECK(take(job.arena, g->ws_zbits, static_cast<size_t>(N) * sizeof(uint64_t), &p));
+    zbits = static_cast<uint64_t*>(p);
     hipLaunchKernelGGL(k_sign_bits<T>, dim3(grid_for(N, kWavesPerBlock)), dim3(kBlock), 0, st, N, kp, Z, zbits);
     ND_LAUNCH_CHECK();
   }
@@ -1091,6 +1131,10 @@ nd_status setup_block(nd_graph* g, const MomentJob& job, int j0, int kb, hipStre
   int32_t* zcls = nullptr;
   T* zcls_val = nullptr;
   if (filt) {
+    if (job.arena) {
+      set_error("internal: motif filtering on the fixed workspace");
+      return ND_EUNSUPPORTED;
+    }
     if (zmode) {
       const size_t nc = static_cast<size_t>(job.motifs->n_classes);
       ND_CHECK(g->ws_zcls.ensure(static_cast<size_t>(N) * 4 + 256 + nc * kp * sizeof(T)));
@@ -1132,7 +1176,7 @@ nd_status setup_block(nd_graph* g, const MomentJob& job, int j0, int kb, hipStre
   a.zbits = zbits;
   a.zcls = zcls;
   a.zcls_val = zcls_val;
-  a.chunk_part = g->ws_chunk.p;
+  a.chunk_part = p_chunk;
   a.z = Z;
   a.kp = kp;
   a.k_batch = kb;
@@ -1157,7 +1201,6 @@ nd_status setup_block(nd_graph* g, const MomentJob& job, int j0, int kb, hipStre
 
 template <typename T>
 nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
-  constexpr int PPL = 16 / sizeof(T);
   const int64_t N = g->n;
   const int M = job.M;
   double* mu_pp = job.mu_pp;
@@ -1178,12 +1221,20 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
   const int64_t ld_raw = 2 * (static_cast<int64_t>(last) + 1);
   const size_t n_pp = job.mu_pp ? 0 : static_cast<size_t>(job.k) * M;
   const size_t n_raw = job.doubling ? static_cast<size_t>(job.k) * ld_raw : 0;
-  if (n_pp + n_raw) ND_CHECK(g->ws_misc.ensure((n_pp + n_raw) * sizeof(double)));
-  if (!mu_pp) mu_pp = g->ws_misc.as<double>();
-  double* raw = job.doubling ? g->ws_misc.as<double>() + n_pp : nullptr;
+  double* misc = nullptr;
+  if (n_pp + n_raw) {
+    void* p = nullptr;
+    ND_CHECK(take(job.arena, g->ws_misc, (n_pp + n_raw) * sizeof(double), &p));
+    misc = static_cast<double*>(p);
+  }
+  if (!mu_pp) mu_pp = misc;
+  double* raw = job.doubling ? misc + n_pp : nullptr;
   const int bmax = max_block_probes();
+  // each probe block reuses the arena space after the call-wide buffers
+  const size_t arena_mark = job.arena ? job.arena->used : 0;
   for (int j0 = 0; j0 < job.k; j0 += bmax) {
     const int kb = job.k - j0 < bmax ? job.k - j0 : bmax;
+    if (job.arena) job.arena->used = arena_mark;
     BlockSetup<T> bs;
     ND_CHECK(setup_block<T>(g, job, j0, kb, st, bs));
     const int kp = bs.kp, L = bs.L, grid = bs.grid, zmode = bs.zmode;
@@ -1194,10 +1245,16 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     const int NSd = job.doubling ? 2 : 1;          // sums per probe of the step launches
     const int64_t per_step = slots * kp * NSd;
     int R = static_cast<int>((int64_t(64) << 20) / (per_step * 8));
+    if (job.arena) {  // as many launches as the rest of the arena holds
+      const size_t used = (job.arena->used + 255) & ~size_t(255);
+      const int64_t fit = used < job.arena->cap ? static_cast<int64_t>((job.arena->cap - used) / (per_step * 8)) : 0;
+      if (fit < R) R = static_cast<int>(fit);
+    }
     if (R < 1) R = 1;
     if (R > last + 1) R = last + 1;
-    ND_CHECK(g->ws_partial.ensure(static_cast<size_t>(R) * per_step * sizeof(double)));
-    double* partial = g->ws_partial.as<double>();
+    void* p_partial = nullptr;
+    ND_CHECK(take(job.arena, g->ws_partial, static_cast<size_t>(R) * per_step * sizeof(double), &p_partial));
+    double* partial = static_cast<double*>(p_partial);
     // unit probes: z^T T_m(H) z is the PDOS moment itself, no 1/N
     const double inv_n = job.unit_nodes ? 1.0 : 1.0 / static_cast<double>(N);
     // LDOS terms go through a staging block of S launches (at most 1 GiB)
@@ -1205,8 +1262,9 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     if (job.ldos) {
       const int64_t per_launch = N * 8 * (job.ldos_sq ? 2 : 1);
       S = ldos_stage_launches(per_launch, last + 1);
-      ND_CHECK(g->ws_stage.ensure(static_cast<size_t>(S) * per_launch));
-      a.stage = g->ws_stage.as<double>();
+      void* p_stage = nullptr;
+      ND_CHECK(take(job.arena, g->ws_stage, static_cast<size_t>(S) * per_launch, &p_stage));
+      a.stage = static_cast<double*>(p_stage);
       a.stage_sq = job.ldos_sq ? a.stage + static_cast<int64_t>(S) * N : nullptr;
     }
     for (int m = 0; m <= last; ++m) {
@@ -1507,6 +1565,73 @@ nd_status run_lanczos(nd_graph* g, const MomentJob& job, int K, double* alpha, d
   return ND_OK;
 }
 
+// ------------------------------------------------ allocation-free workspace
+// The fixed device workspace of nd_cheb_moments_noalloc: every GPU the
+// library runs on holds one copy until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in
+// for the symbol): it takes the device address from hipGetSymbolAddress,
+// once per device, and uses that.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+nd_status scratch_address(int dev, char** out) {
+  ND_REQUIRE(dev >= 0 && dev < kMaxDevices, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    ND_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    ND_REQUIRE(p != nullptr, "hipGetSymbolAddress returned no address for the fixed workspace");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[dev]);
+  return ND_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bytes the allocation-free path takes from the arena for this call (the
+// largest probe block, one launch of moment partials), or an error when a
+// probe block has no schedule yet.
+template <typename T>
+nd_status noalloc_bytes(const nd_graph* g, const MomentJob& job, size_t* need) {
+  constexpr int PPL = 16 / sizeof(T);
+  const int64_t N = g->n;
+  const int M = job.M;
+  const int last = job.doubling ? M / 2 : M - 1;
+  const int64_t ld_raw = 2 * (static_cast<int64_t>(last) + 1);
+  size_t misc = 0;
+  if (!job.mu_pp) misc += static_cast<size_t>(job.k) * M;
+  if (job.doubling) misc += static_cast<size_t>(job.k) * ld_raw;
+  size_t worst = 0;
+  const int bmax = max_block_probes();
+  for (int j0 = 0; j0 < job.k; j0 += bmax) {
+    const int kb = job.k - j0 < bmax ? job.k - j0 : bmax;
+    const int kp = pow2_at_least(kb < PPL ? PPL : kb);
+    const int L = kp * static_cast<int>(sizeof(T)) / 16;
+    auto it = g->sched.find(L);
+    if (it == g->sched.end() || !g->internal) {
+      set_error("nd_cheb_moments_noalloc: the graph has no row schedule for blocks of %d probes yet: run "
+                "nd_cheb_moments once on it with the same probe count first", kp);
+      return ND_EINVAL;
+    }
+    const Schedule* sc = it->second.get();
+    const int grid = grid_for(sc->n_items > 0 ? sc->n_items : 1, kWavesPerBlock, step_grid<T>(L));
+    const int split_blocks = sc->n_split > 0 ? grid_for(sc->n_split, kWavesPerBlock, grid) : 0;
+    const int64_t per_step = (static_cast<int64_t>(grid) + split_blocks) * kp * (job.doubling ? 2 : 1);
+    size_t b = align256(3 * static_cast<size_t>(N) * kp * sizeof(T));
+    b += align256(static_cast<size_t>(sc->n_chunks > 0 ? sc->n_chunks : 1) * kp * sizeof(double));
+    if (!job.gaussian) b += align256(static_cast<size_t>(N) * sizeof(uint64_t));
+    b += align256(static_cast<size_t>(per_step) * sizeof(double));
+    if (b > worst) worst = b;
+  }
+  *need = align256(misc * sizeof(double)) + worst;
+  return ND_OK;
+}
+
 nd_status check_common(const nd_graph* g, const nd_motifs* motifs, int32_t n_probes, int32_t n_moments,
                        uint32_t flags, const char* who) {
   ND_REQUIRE(g != nullptr, "%s: graph is NULL", who);
@@ -1604,6 +1729,37 @@ nd_status nd_cheb_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
   return nd::run_moments<float>(gm, job, nd::as_stream(stream));
 }
 
+nd_status nd_cheb_moments_noalloc(const nd_graph* g, int32_t n_probes, int32_t n_moments, uint64_t probe_seed,
+                                  uint32_t flags, double* mu, double* mu_pp, void* stream) {
+  nd::clear_error();
+  ND_CHECK(nd::check_common(g, nullptr, n_probes, n_moments, flags, "nd_cheb_moments_noalloc"));
+  ND_REQUIRE((flags & ND_TIME_STEPS) == 0,
+             "nd_cheb_moments_noalloc: ND_TIME_STEPS is not available here (it creates events)");
+  ND_REQUIRE(mu != nullptr || mu_pp != nullptr, "nd_cheb_moments_noalloc: mu and mu_pp are both NULL");
+  nd::MomentJob job;
+  job.k = n_probes;
+  job.M = n_moments;
+  job.seed = probe_seed;
+  job.gaussian = (flags & ND_PROBE_GAUSSIAN) != 0;
+  job.mu = mu;
+  job.mu_pp = mu_pp;
+  job.doubling = (flags & ND_MOMENT_DOUBLING) != 0;
+  const bool f64 = (flags & ND_STATE_FP64) != 0;
+  size_t need = 0;
+  ND_CHECK(f64 ? nd::noalloc_bytes<double>(g, job, &need) : nd::noalloc_bytes<float>(g, job, &need));
+  ND_REQUIRE(need <= nd::kNoAllocBytes,
+             "nd_cheb_moments_noalloc: this call needs %zu bytes of workspace, more than the fixed %zu (the "
+             "recurrence state alone is 3 x N x padded probes x %d bytes); use nd_cheb_moments",
+             need, nd::kNoAllocBytes, f64 ? 8 : 4);
+  nd::Arena arena;
+  ND_CHECK(nd::scratch_address(g->device, &arena.base));
+  arena.cap = nd::kNoAllocBytes;
+  job.arena = &arena;
+  nd_graph* gm = const_cast<nd_graph*>(g);
+  if (f64) return nd::run_moments<double>(gm, job, nd::as_stream(stream));
+  return nd::run_moments<float>(gm, job, nd::as_stream(stream));
+}
+
 nd_status nd_pdos_nodes(const nd_graph* g, const int32_t* nodes, int32_t n_nodes, int32_t n_moments, uint32_t flags,
                         double* pdos, void* stream) {
   nd::clear_error();
@@ -1638,6 +1794,9 @@ nd_status nd_ldos_moments(const nd_graph* g, const nd_motifs* motifs, int32_t n_
   ND_REQUIRE((flags & ND_MOMENT_DOUBLING) == 0,
              "nd_ldos_moments: ND_MOMENT_DOUBLING applies to global moments only (the per-node estimate "
              "needs every T_m(H) z)");
+  ND_REQUIRE(cv_g == nullptr || motifs == nullptr || motifs->n_classes == 0,
+             "nd_ldos_moments: a control variate cannot be combined with twin filtering (a projected probe "
+             "entry of a class member has mean square 1/|C|, so g (1 - z_i^2) would bias its row)");
   nd::MomentJob job;
   job.motifs = motifs;
   job.k = n_probes;

@@ -101,7 +101,9 @@ __global__ __launch_bounds__(kBlock) void k_recon_gemm(const double* __restrict_
 #pragma unroll
     for (int u = 0; u < kPB; ++u) {
       const int t = threadIdx.x + u * kBlock, k = t / kTC, c = t % kTC;
-      rb[u] = Wt[static_cast<int64_t>(m0 + k) * cpad + c0 + c];
+      // only the launch's ncols columns exist past c0 (a tile that starts
+      // inside the table, e.g. at the density points, ends before cpad)
+      rb[u] = c < ncols ? Wt[static_cast<int64_t>(m0 + k) * cpad + c0 + c] : 0.0;
     }
   };
   fetch(0);
