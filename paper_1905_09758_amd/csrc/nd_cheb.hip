@@ -1582,8 +1582,14 @@ nd_status scratch_address(int dev, char** out) {
   ND_REQUIRE(dev >= 0 && dev < kMaxDevices, "device %d out of range", dev);
   std::lock_guard<std::mutex> lock(g_scratch_mu);
   if (!g_scratch_ptr[dev]) {
+    // the symbol's address is per device: look it up with `dev` current
+    int cur = -1;
+    ND_HIP(hipGetDevice(&cur));
+    if (cur != dev) ND_HIP(hipSetDevice(dev));
     void* p = nullptr;
-    ND_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) ND_HIP(hipSetDevice(cur));
+    ND_HIP(e);
     ND_REQUIRE(p != nullptr, "hipGetSymbolAddress returned no address for the fixed workspace");
     g_scratch_ptr[dev] = p;
   }
