@@ -296,9 +296,12 @@ __device__ inline void row_probes(const StepArgs& a, bool own, int64_t r, int q,
 }
 
 // Finish row r: X_{m+1} = 2/d * acc - X_{m-1} (or acc/d on the first step)
-// evaluated in the accumulator type A, stored in place, then the moment
-// epilogue on Y = sqrt(d) X.  Doubling steps add Y_{m+1}.Y_m and
-// Y_{m+1}.Y_{m+1} per probe instead (T_{m+1} T_m = (T_{2m+1} + T_1)/2 and
+// evaluated in fp64 with one rounding to T, stored in place, then the moment
+// epilogue on Y = sqrt(d) X.  (A scale 2/d rounded to fp32 would carry the
+// same relative error into every step of the row: a fixed perturbation of
+// D^{-1} A that moves the eigenvalue 1 by O(2^-24), which T_m, whose slope at
+// 1 is m^2, turns into per-node errors growing like m^2 2^-24.)
+// Doubling steps add Y_{m+1}.Y_m and Y_{m+1}.Y_{m+1} per probe instead (T_{m+1} T_m = (T_{2m+1} + T_1)/2 and
 // T_{m+1}^2 = (T_{2m+2} + T_0)/2 turn them into two moments each).
 // Lanczos steps (ZM == 3) store W = c1 D^{-1} A X - c2 X_prev with per-probe
 // scales c1, c2 of the stored vectors, and add d c1 X(r) W(r) per probe (the
@@ -311,13 +314,13 @@ __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_
     if (own) {
       T* xo = reinterpret_cast<T*>(a.xio) + r * a.kp + q * PPL;
       T xn[PPL];
-      const A invd = A(1) / static_cast<A>(d);
+      const double invd = 1.0 / static_cast<double>(d);
 #pragma unroll
       for (int c = 0; c < PPL; ++c) {
         const int j = q * PPL + c;
-        const A c1 = static_cast<A>(a.lz[j]), c2 = static_cast<A>(a.lz[a.kp + j]);
-        xn[c] = a.first ? static_cast<T>(acc[c] * invd * c1)
-                        : static_cast<T>(acc[c] * invd * c1 - c2 * static_cast<A>(o.xp[c]));
+        const double c1 = a.lz[j], c2 = a.lz[a.kp + j];
+        const double s = static_cast<double>(acc[c]) * invd * c1;
+        xn[c] = a.first ? static_cast<T>(s) : static_cast<T>(s - c2 * static_cast<double>(o.xp[c]));
       }
       store16_nt<T>(xo, xn);
       const double dd = static_cast<double>(d);
@@ -334,14 +337,15 @@ __device__ inline void finish_row(const StepArgs& a, bool own, int64_t r, int64_
   if (own) {
     T* xo = reinterpret_cast<T*>(a.xio) + r * a.kp + q * PPL;
     T xn[PPL];
-    const A invd = A(1) / static_cast<A>(d);
+    const double invd = 1.0 / static_cast<double>(d);
     if (a.first) {
 #pragma unroll
-      for (int c = 0; c < PPL; ++c) xn[c] = static_cast<T>(acc[c] * invd);
+      for (int c = 0; c < PPL; ++c) xn[c] = static_cast<T>(static_cast<double>(acc[c]) * invd);
     } else {
-      const A two_invd = A(2) * invd;
+      const double two_invd = 2.0 * invd;
 #pragma unroll
-      for (int c = 0; c < PPL; ++c) xn[c] = static_cast<T>(two_invd * acc[c] - static_cast<A>(o.xp[c]));
+      for (int c = 0; c < PPL; ++c)
+        xn[c] = static_cast<T>(two_invd * static_cast<double>(acc[c]) - static_cast<double>(o.xp[c]));
     }
     store16_nt<T>(xo, xn);
     const double sd = sqrt(static_cast<double>(d));

@@ -13,16 +13,25 @@ TOL_FP64 = 1e-10
 EPS32 = 2.0 ** -24
 
 
+# Per-node (LDOS) tolerance of the fp32 recurrence.  Each step rounds X to
+# fp32; the row update 2/d acc - X_{m-1} is formed in fp64, so the operator
+# itself carries no fp32 scale error.  Rounding injected at step s reaches
+# moment m through U_{m-s}(H), which is bounded away from the eigenvalues +-1
+# and equals +-(m-s+1) on them.  Measured (MI355X, fp64 row update, 20 probes,
+# m <= 200): at most 3.2e-6 on ER-2000, BA + twins, R-MAT-12 and WS, so those
+# graphs are held to the stated bar of 1e-5 for every m <= 200.  The star
+# K_{1,3000} is the exception: its spectrum is {-1, 0, 1} and every node carries
+# weight on the +-1 eigenvectors, whose random rounding errors add up like a
+# walk amplified linearly in m; measured max over nodes and m of
+# err / (m^1.5 2^-24) = 0.67 (20 probes, m <= 200) and 1.64 (32 probes,
+# m <= 999), so its envelope is STAR_C m^1.5 2^-24 with STAR_C = 5 (3x).
+STAR_C = 5.0
+
+
 def ldos_tol(M, name):
-    """Per-node moments from the fp32 recurrence.  Each step rounds X to fp32
-    (relative 2^-24); an error injected at step k reaches moment m through
-    U_{m-k}(H), which is as large as m-k+1 on the eigenvalues +-1 (always
-    present: lambda = 1 is the Perron eigenvalue).  The accumulated error is
-    therefore bounded by about m^2 2^-24 where such eigenvectors put their
-    weight on a node (the star's hub); on ordinary graphs it stays below 1e-5
-    up to M = 100."""
-    if name == "star" or M > 100:
-        return max(1e-5, float(M) ** 2 * EPS32)
+    """Largest per-node error allowed for moments m < M."""
+    if name == "star":
+        return max(1e-5, STAR_C * float(max(M - 1, 1)) ** 1.5 * EPS32)
     return 1e-5
 
 
@@ -376,14 +385,13 @@ def test_global_moments_fp64_state(case, nd):
 
 def test_moments_m1000(nd):
     """The precision-study moment count (M = 1000) on a small R-MAT graph.
-    fp64 state: within 1e-9 of the oracle (fp64 rounding, amplified like the
-    fp32 case, stays ~m^2 2^-53).  fp32 state: global moments within 1e-5 up to
-    m = 200 as everywhere; beyond, global and per-node moments within the
-    worst-case envelope m^2 2^-24 (rounding errors reach moment m through
-    U_{m-k}(H), as large as m-k+1 at the eigenvalues +-1; on this small graph
-    the hubs carry a large share of the Perron vector, so the per-node error
-    does grow faster than linearly: about 1% of m^2 2^-24 at m = 999)."""
+    fp64 state: within 1e-9 of the oracle.  fp32 state: global and per-node
+    moments within 1e-5 up to m = 200 (the stated bar); beyond, the documented
+    envelope C1000 m 2^-24: with the row update in fp64 the per-node error
+    grows about linearly (measured max err / (m 2^-24) over 200 < m < 1000 on
+    this graph: 0.43), and C1000 = 1.3 is three times that."""
     import torch
+    C1000 = 1.3
     n, s, d = sg.rmat(12, 8, seed=3)
     g_or = og.build_csr(n, s, d)
     g = nd.nd_build_csr(n, s, d)
@@ -398,11 +406,34 @@ def test_moments_m1000(nd):
     mu32 = _zeros(M, torch.float64)
     nd.nd_ldos_moments(g, None, k, M, 4, 0, ld, mu=mu32)
     err_mu = np.abs(mu32.cpu().numpy() - mu_o)
-    assert err_mu[:201].max() < TOL_MU
     err = np.abs(ld.cpu().numpy().reshape(g.n, M) - C_o).max(axis=0)
-    env = np.maximum(1e-5, np.arange(M, dtype=np.float64) ** 2 * EPS32)
+    assert err_mu[:201].max() < TOL_MU
+    assert err[:201].max() < 1e-5, float(err[:201].max())
+    env = np.maximum(1e-5, C1000 * np.arange(M, dtype=np.float64) * EPS32)
     assert np.all(err <= env), (int(np.argmax(err / env)), float(np.max(err / env)))
     assert np.all(err_mu <= env)
+
+
+@pytest.mark.parametrize("k,M,seed", [(20, 201, 11), (64, 201, 3)])
+def test_ldos_m200(case, nd, k, M, seed):
+    """Every per-node moment up to m = 200 against the oracle: within 1e-5
+    on the ordinary graphs, within the star's documented envelope there."""
+    import torch
+    name, _, g_or, g = case
+    H = og.normalized_adjacency(g_or)
+    Z = orng.rademacher(g_or.n, k, seed)
+    mu_o, _, C_o = kpm.stochastic_moments(H, Z, M)
+    ld = _zeros(g.n * M, torch.float64)
+    mu = _zeros(M, torch.float64)
+    nd.nd_ldos_moments(g, None, k, M, seed, 0, ld, mu=mu)
+    E = np.abs(ld.cpu().numpy().reshape(g.n, M) - C_o)
+    assert np.max(np.abs(mu.cpu().numpy() - mu_o)) < TOL_MU
+    if name == "star":
+        m = np.arange(M, dtype=np.float64)
+        env = np.maximum(1e-5, STAR_C * m ** 1.5 * EPS32)
+        assert np.all(E.max(axis=0) <= env)
+    else:
+        assert E.max() < 1e-5, (name, float(E.max()), int(np.argmax(E.max(axis=0))))
 
 
 @pytest.mark.parametrize("k,M", [(20, 50), (70, 12)])
