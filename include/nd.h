@@ -411,10 +411,47 @@ nd_status nd_reconstruct(const double* mu, int64_t n_rows, int32_t n_moments, ui
  * degree, max neighbour degree, local clustering 2t/(d(d-1)) (0 if d < 2),
  * number of nodes at distance exactly 2).  If mean/std (device float [5])
  * are given, each column is then standardised as (x - mean) / std.
- * Needs N <= 524288 (per-node neighbourhood bitmaps live in LDS);
- * larger graphs return ND_EUNSUPPORTED. */
+ * Cost O(d_i + sum_{j in N(i)} d_j) per node.  Neighbourhood bitmaps live in
+ * LDS up to N = 524288 and otherwise in a temporary device workspace of at
+ * most 4 GiB (2 x N bits per block, fewer blocks for larger graphs);
+ * ND_EUNSUPPORTED only if one block's bitmaps exceed that. */
 nd_status nd_node_features(const nd_graph* g, const float* mean, const float* std, float* feat,
                            void* stream);
+
+/* Exact diagonal of the first Chebyshev polynomials of H (Sec. 3.1; the
+ * exactly known part of a diagonal control variate).  For every node i and
+ * m < n_cols (1..4): cv_g[i * ld + m] = T_m(H)_ii, i.e.
+ *   T_0: 1;  T_1: 0 (no self loops);  T_2: 2 sum_{j in N(i)} 1/(d_i d_j) - 1;
+ *   T_3: 4 sum_{j in N(i)} sum_{k in N(i) & N(j)} 1/(d_i d_j d_k).
+ * cv_g is device float [N][ld] (compact node order), typically an MLP
+ * output whose first columns this overwrites.  Sums in fp64, fixed order.
+ * Same workspace as nd_node_features.  Errors: ND_EINVAL for n_cols outside
+ * 1..4 or ld < n_cols. */
+nd_status nd_cv_exact_diag(const nd_graph* g, float* cv_g, int64_t ld, int32_t n_cols, void* stream);
+
+/* The motif part of the diagonal (Sec. 3.4): for every member i of a class
+ * C of `motifs` and m < n_cols,
+ *   cv_g[i * ld + m] += scale (1 - 1/|C|) T_m(lambda_C)
+ * (paired classes: T_m(lambda_C) at even m only), the exact contribution of
+ * the class's removed eigenvectors to T_m(H)_ii -- the same term
+ * nd_ldos_moments adds back to filtered per-node moments.  A control variate
+ * uses it to split g into this exactly known part and a learned remainder
+ * (scale -1 on training targets, +1 on the prediction).  cv_g: device float
+ * [N][ld], compact node order.  Errors: ND_EINVAL for n_cols < 1 or
+ * ld < n_cols. */
+nd_status nd_motif_diag(const nd_motifs* motifs, float* cv_g, int64_t ld, int32_t n_cols, double scale,
+                        void* stream);
+
+/* Per-probe variance of per-node estimates (not in the paper; the figure of
+ * merit of a control variate): from one run's ldos and ldos_sq
+ * (nd_ldos_moments, device double [n][n_moments]) with k = n_probes >= 2,
+ *   s2_im = k/(k-1) (ldos_sq_im - ldos_im^2),
+ * out[0] = mean over nodes and m in [m_lo, n_moments) of s2 (device double),
+ * per_m (device double [n_moments] or NULL) = mean over nodes for each m.
+ * Fixed-order sums.  n_moments <= 1024.  Probes needed for a target
+ * variance v: out[0] / v. */
+nd_status nd_ldos_variance(const double* ldos, const double* ldos_sq, int64_t n, int32_t n_moments,
+                           int32_t m_lo, int32_t n_probes, double* out, double* per_m, void* stream);
 
 /* Column statistics of x device float [n_rows][n_cols] (n_cols <= 16):
  * mean[c] and std[c] = sqrt(max(E[x^2] - mean^2, 1e-12)) as device floats,

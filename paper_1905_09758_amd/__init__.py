@@ -39,7 +39,7 @@ EXPORTS = (
     "nd_graph_free",
     "nd_motif_filter", "nd_motif_info", "nd_motif_export", "nd_motif_export_lambda", "nd_motifs_free",
     "nd_make_probes",
-    "nd_cheb_moments", "nd_cheb_moments_noalloc", "nd_ldos_moments", "nd_pdos_nodes", "nd_pdos_nested", "nd_gql", "nd_gql_pdos", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_column_stats",
+    "nd_cheb_moments", "nd_cheb_moments_noalloc", "nd_ldos_moments", "nd_pdos_nodes", "nd_pdos_nested", "nd_gql", "nd_gql_pdos", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_cv_exact_diag", "nd_motif_diag", "nd_ldos_variance", "nd_column_stats",
     "nd_mlp_forward", "nd_mlp_grad", "nd_adam_step", "nd_last_error",
 )
 
@@ -93,6 +93,9 @@ _sig("nd_gql_density", [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _dbl, _dbl, _vp, 
 _sig("nd_reconstruct", [_vp, _i64, _i32, _u32, _vp, _vp, _i32, _i32, _dbl, _dbl, _vp, _i32, _vp, _vp])
 _sig("nd_last_error", [], ctypes.c_char_p)
 _sig("nd_node_features", [_vp, _vp, _vp, _vp, _vp])
+_sig("nd_cv_exact_diag", [_vp, _vp, _i64, _i32, _vp])
+_sig("nd_motif_diag", [_vp, _vp, _i64, _i32, ctypes.c_double, _vp])
+_sig("nd_ldos_variance", [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp])
 _sig("nd_column_stats", [_vp, _i64, _i32, _vp, _vp, _vp])
 _sig("nd_mlp_forward", [_vp, _vp, _i64, _i32, _vp, _vp])
 _sig("nd_mlp_grad", [_vp, _vp, _vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp])
@@ -385,6 +388,30 @@ def nd_node_features(g: Graph, feat, mean=None, std=None, stream=None):
     _check(_lib.nd_node_features(g.handle, _dev(mean, torch.float32, N_FEAT, "mean"),
                                  _dev(std, torch.float32, N_FEAT, "std"), _dev(feat, torch.float32, g.n * N_FEAT, "feat"),
                                  _stream(stream)), "nd_node_features")
+
+
+def nd_cv_exact_diag(g: Graph, cv_g, ld: int, n_cols: int = 4, stream=None):
+    """Overwrite columns 0..n_cols-1 of cv_g [N][ld] with the exact T_m(H)_ii."""
+    import torch
+    _check(_lib.nd_cv_exact_diag(g.handle, _dev(cv_g, torch.float32, g.n * ld, "cv_g"), ld, n_cols,
+                                 _stream(stream)), "nd_cv_exact_diag")
+
+
+def nd_motif_diag(m: Motifs, cv_g, ld: int, n_cols: int, scale: float = 1.0, stream=None):
+    """cv_g [N][ld] += scale (1 - 1/|C|) T_m(lambda_C) for class members, m < n_cols."""
+    import torch
+    _check(_lib.nd_motif_diag(m.handle, _dev(cv_g, torch.float32, m.graph.n * ld, "cv_g"), ld, n_cols,
+                              float(scale), _stream(stream)), "nd_motif_diag")
+
+
+def nd_ldos_variance(ldos, ldos_sq, n: int, n_moments: int, m_lo: int, n_probes: int, out, per_m=None,
+                     stream=None):
+    import torch
+    _check(_lib.nd_ldos_variance(_dev(ldos, torch.float64, n * n_moments, "ldos"),
+                                 _dev(ldos_sq, torch.float64, n * n_moments, "ldos_sq"), n, n_moments, m_lo,
+                                 n_probes, _dev(out, torch.float64, 1, "out"),
+                                 _dev(per_m, torch.float64, n_moments, "per_m"), _stream(stream)),
+           "nd_ldos_variance")
 
 
 def nd_column_stats(x, n_rows: int, n_cols: int, mean, std, stream=None):

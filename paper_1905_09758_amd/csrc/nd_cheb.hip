@@ -866,35 +866,6 @@ __global__ __launch_bounds__(kBlock) void k_ldos_flush(const double* __restrict_
   }
 }
 
-// ldos[i][m] += (1 - 1/|C|) T_m(lambda_C) for every member i of a class C;
-// a paired class (eigenvalues +-lambda_C, half each) adds
-// (1 - 1/|C|) (T_m(lambda) + T_m(-lambda)) / 2, i.e. T_m(lambda) at even m.
-__global__ __launch_bounds__(kBlock) void k_ldos_spike(const int64_t* __restrict__ class_ptr,
-                                                       const int32_t* __restrict__ members,
-                                                       const double* __restrict__ class_lambda,
-                                                       const int32_t* __restrict__ class_paired, int64_t n_classes,
-                                                       int64_t n_members, int M, double* __restrict__ ldos) {
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n_members;
-       p += static_cast<int64_t>(gridDim.x) * kBlock) {
-    int64_t lo = 0, hi = n_classes;  // class c with class_ptr[c] <= p < class_ptr[c+1]
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) / 2;
-      if (class_ptr[mid] <= p) lo = mid; else hi = mid;
-    }
-    const double w = 1.0 - 1.0 / static_cast<double>(class_ptr[lo + 1] - class_ptr[lo]);
-    const double x = class_lambda[lo];
-    const bool pair = class_paired[lo] != 0;
-    double* row = ldos + static_cast<int64_t>(members[p]) * M;
-    double t0 = 1.0, t1 = x;
-    for (int m = 0; m < M; ++m) {
-      if (!pair || (m & 1) == 0) row[m] += w * t0;
-      const double t2 = 2.0 * x * t1 - t0;
-      t0 = t1;
-      t1 = t2;
-    }
-  }
-}
-
 int pow2_at_least(int x) {
   int p = 1;
   while (p < x) p <<= 1;
@@ -1351,9 +1322,10 @@ nd_status run_moments(nd_graph* g, const MomentJob& job, hipStream_t st) {
     ND_LAUNCH_CHECK();
   }
   if (job.ldos && job.motifs && job.motifs->n_classes > 0) {
-    hipLaunchKernelGGL(k_ldos_spike, dim3(grid_for(job.motifs->n_members, kBlock)), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL(k_motif_diag<double>, dim3(grid_for(job.motifs->n_members, kBlock)), dim3(kBlock), 0, st,
                        job.motifs->class_ptr, job.motifs->members, job.motifs->class_lambda,
-                       job.motifs->class_paired, job.motifs->n_classes, job.motifs->n_members, M, job.ldos);
+                       job.motifs->class_paired, job.motifs->n_classes, job.motifs->n_members,
+                       static_cast<int64_t>(M), M, 1.0, job.ldos);
     ND_LAUNCH_CHECK();
   }
   return ND_OK;

@@ -195,6 +195,40 @@ struct nd_motifs {
 };
 
 namespace nd {
+// out[i * ld + m] += scale (1 - 1/|C|) T_m(lambda_C), m < n_cols, for every
+// member i of a motif class C: the part of T_m(H)_ii that the class's removed
+// eigenvectors carry (Sec. 3.4).  A paired class (eigenvalues +-lambda_C,
+// half each) adds (1 - 1/|C|) (T_m(lambda) + T_m(-lambda)) / 2, i.e.
+// T_m(lambda) at even m and nothing at odd m.  T_m by the three-term
+// recurrence in fp64.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_motif_diag(const int64_t* __restrict__ class_ptr,
+                                                       const int32_t* __restrict__ members,
+                                                       const double* __restrict__ class_lambda,
+                                                       const int32_t* __restrict__ class_paired, int64_t n_classes,
+                                                       int64_t n_members, int64_t ld, int n_cols, double scale,
+                                                       T* __restrict__ out) {
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n_members;
+       p += static_cast<int64_t>(gridDim.x) * kBlock) {
+    int64_t lo = 0, hi = n_classes;  // class c with class_ptr[c] <= p < class_ptr[c+1]
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) / 2;
+      if (class_ptr[mid] <= p) lo = mid; else hi = mid;
+    }
+    const double w = scale * (1.0 - 1.0 / static_cast<double>(class_ptr[lo + 1] - class_ptr[lo]));
+    const double x = class_lambda[lo];
+    const bool pair = class_paired[lo] != 0;
+    T* row = out + static_cast<int64_t>(members[p]) * ld;
+    double t0 = 1.0, t1 = x;
+    for (int m = 0; m < n_cols; ++m) {
+      if (!pair || (m & 1) == 0) row[m] = static_cast<T>(static_cast<double>(row[m]) + w * t0);
+      const double t2 = 2.0 * x * t1 - t0;
+      t0 = t1;
+      t1 = t2;
+    }
+  }
+}
+
 nd_status get_internal(nd_graph* g, hipStream_t st, Internal** out);
 nd_status get_schedule(nd_graph* g, int L, hipStream_t st, Schedule** out);
 // Lanczos coefficients of every probe (Sec. 3.2), on the sparse step kernels:

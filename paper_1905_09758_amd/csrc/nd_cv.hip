@@ -15,7 +15,6 @@ namespace {
 
 constexpr int kFeat = 5;
 constexpr int kWidth = 128;
-constexpr int64_t kMaxFeatNodes = 524288;  // two N-bit bitmaps in LDS
 
 struct Layout {
   int64_t w1, b1, w2, b2, w3, b3, total;
@@ -31,88 +30,225 @@ struct Layout {
 };
 
 // ------------------------------------------------------------------ features
-// One block per node i: bitmap A marks N(i), bitmap B marks nodes at distance
-// exactly 2.  Each wavefront walks the neighbour lists of some j in N(i);
-// a k in N(j) that is also in N(i) closes a triangle (each counted twice).
+// One block per node i (grid-stride).  Bitmap A marks N(i), bitmap B the
+// nodes at distance exactly 2.  They live in LDS when the graph fits
+// (2 x N bits <= kLdsBitmapBytes), otherwise in the block's own slice of a
+// device workspace; either way a block clears its bitmaps once, then clears
+// only the words a node touched, and the distance-2 count comes from the
+// atomicOr return values, so node i costs O(d_i + sum_{j in N(i)} d_j).
+// Each wavefront walks the neighbour list of some j in N(i); a k in N(j)
+// that is also in N(i) closes a triangle (each counted twice).
+//
+// Optionally (diag != null) the same walk gives the exact diagonal of the
+// first Chebyshev polynomials of H = D^{-1/2} A D^{-1/2} (no self loops):
+//   T_0(H)_ii = 1,  T_1(H)_ii = H_ii = 0,
+//   T_2(H)_ii = 2 (H^2)_ii - 1 = 2 sum_{j in N(i)} 1 / (d_i d_j) - 1,
+//   T_3(H)_ii = 4 (H^3)_ii - 3 H_ii = 4 sum_{j in N(i)} sum_{k in N(i) & N(j)} 1 / (d_i d_j d_k),
+// written to diag[i * ld + m] for m < n_diag (<= 4).  All sums have a fixed
+// order (per lane, then lanes and wavefronts in a fixed tree).
+constexpr size_t kLdsBitmapBytes = 128 * 1024;
+
+template <bool LDS>
+__device__ inline uint32_t bm_or(uint32_t* p, uint32_t bit) {
+  if constexpr (LDS) return atomicOr(p, bit);
+  else return __hip_atomic_fetch_or(p, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool LDS>
+__device__ inline uint32_t bm_get(const uint32_t* p) {
+  if constexpr (LDS) return *p;
+  else return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool LDS>
+__device__ inline void bm_clear(uint32_t* p) {
+  if constexpr (LDS) *p = 0u;
+  else __hip_atomic_store(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool LDS>
 __global__ __launch_bounds__(kBlock) void k_features(const int64_t* __restrict__ row_ptr,
-                                                     const int32_t* __restrict__ col, int64_t n, int words,
-                                                     const float* __restrict__ mean, const float* __restrict__ sdev,
-                                                     float* __restrict__ feat) {
-  extern __shared__ uint32_t bm[];
-  uint32_t* A = bm;
-  uint32_t* B = bm + words;
-  __shared__ unsigned long long red_sum[kBlock / kWave];
-  __shared__ unsigned long long red_tri[kBlock / kWave];
-  __shared__ long long red_max[kBlock / kWave];
-  __shared__ unsigned long long red_two[kBlock / kWave];
+                                                     const int32_t* __restrict__ col, int64_t n, int64_t words,
+                                                     uint32_t* __restrict__ gbm, const float* __restrict__ mean,
+                                                     const float* __restrict__ sdev, float* __restrict__ feat,
+                                                     float* __restrict__ diag, int64_t ld, int n_diag) {
+  extern __shared__ uint32_t lbm[];
+  uint32_t* A = LDS ? lbm : gbm + static_cast<int64_t>(blockIdx.x) * 2 * words;
+  uint32_t* B = A + words;
+  constexpr int NW = kBlock / kWave;
+  __shared__ unsigned long long red_u[3][NW];
+  __shared__ long long red_max[NW];
+  __shared__ double red_d[2][NW];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const bool want_two = feat != nullptr;
+  for (int64_t w = tid; w < 2 * words; w += kBlock) bm_clear<LDS>(A + w);
+  __syncthreads();
   for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-    for (int w = tid; w < 2 * words; w += kBlock) bm[w] = 0u;
-    __syncthreads();
     const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1], d = e1 - e0;
     unsigned long long dsum = 0;
     long long dmax = 0;
+    double inv_sum = 0.0;
     for (int64_t t = e0 + tid; t < e1; t += kBlock) {
       const int32_t j = col[t];
-      atomicOr(&A[j >> 5], 1u << (j & 31));
+      bm_or<LDS>(&A[j >> 5], 1u << (j & 31));
       const long long dj = row_ptr[j + 1] - row_ptr[j];
       dsum += static_cast<unsigned long long>(dj);
       dmax = dj > dmax ? dj : dmax;
+      inv_sum += 1.0 / static_cast<double>(dj);
     }
     __syncthreads();
-    unsigned long long tri = 0;
-    for (int64_t t = e0 + wid; t < e1; t += kBlock / kWave) {
+    unsigned long long tri = 0, two = 0;
+    double tri_w = 0.0;
+    for (int64_t t = e0 + wid; t < e1; t += NW) {
       const int32_t j = col[t];
-      for (int64_t u = row_ptr[j] + lane; u < row_ptr[j + 1]; u += kWave) {
+      const int64_t u0 = row_ptr[j], u1 = row_ptr[j + 1];
+      const double inv_dj = 1.0 / static_cast<double>(u1 - u0);
+      for (int64_t u = u0 + lane; u < u1; u += kWave) {
         const int32_t k = col[u];
-        if (A[k >> 5] & (1u << (k & 31)))
+        const uint32_t bit = 1u << (k & 31);
+        if (bm_get<LDS>(&A[k >> 5]) & bit) {
           tri++;
-        else if (k != i)
-          atomicOr(&B[k >> 5], 1u << (k & 31));
+          if (diag) tri_w += inv_dj / static_cast<double>(row_ptr[k + 1] - row_ptr[k]);
+        } else if (want_two && k != i) {
+          if (!(bm_or<LDS>(&B[k >> 5], bit) & bit)) two++;
+        }
       }
     }
     __syncthreads();
-    unsigned long long two = 0;
-    for (int w = tid; w < words; w += kBlock) two += static_cast<unsigned long long>(__popc(B[w]));
+    // clear what this node set
+    for (int64_t t = e0 + tid; t < e1; t += kBlock) bm_clear<LDS>(&A[col[t] >> 5]);
+    if (want_two)
+      for (int64_t t = e0 + wid; t < e1; t += NW) {
+        const int32_t j = col[t];
+        for (int64_t u = row_ptr[j] + lane; u < row_ptr[j + 1]; u += kWave) bm_clear<LDS>(&B[col[u] >> 5]);
+      }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
       dsum += __shfl_xor(dsum, off, kWave);
       tri += __shfl_xor(tri, off, kWave);
       two += __shfl_xor(two, off, kWave);
+      inv_sum += __shfl_xor(inv_sum, off, kWave);
+      tri_w += __shfl_xor(tri_w, off, kWave);
       const long long o = __shfl_xor(dmax, off, kWave);
       dmax = o > dmax ? o : dmax;
     }
     if (lane == 0) {
-      red_sum[wid] = dsum;
-      red_tri[wid] = tri;
-      red_two[wid] = two;
+      red_u[0][wid] = dsum;
+      red_u[1][wid] = tri;
+      red_u[2][wid] = two;
       red_max[wid] = dmax;
+      red_d[0][wid] = inv_sum;
+      red_d[1][wid] = tri_w;
     }
     __syncthreads();
     if (tid == 0) {
       unsigned long long S = 0, T = 0, W = 0;
       long long X = 0;
-      for (int w = 0; w < kBlock / kWave; ++w) {
-        S += red_sum[w];
-        T += red_tri[w];
-        W += red_two[w];
+      double IS = 0.0, TW = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        S += red_u[0][w];
+        T += red_u[1][w];
+        W += red_u[2][w];
         X = red_max[w] > X ? red_max[w] : X;
+        IS += red_d[0][w];
+        TW += red_d[1][w];
       }
       const double dd = static_cast<double>(d);
-      const double t_i = static_cast<double>(T) / 2.0;
-      double f[kFeat];
-      f[0] = log1p(dd);
-      f[1] = log1p(static_cast<double>(S) / dd);
-      f[2] = log1p(static_cast<double>(X));
-      f[3] = log1p(d >= 2 ? 2.0 * t_i / (dd * (dd - 1.0)) : 0.0);
-      f[4] = log1p(static_cast<double>(W));
-      for (int c = 0; c < kFeat; ++c) {
-        float v = static_cast<float>(f[c]);
-        if (mean) v = (v - mean[c]) / sdev[c];
-        feat[i * kFeat + c] = v;
+      if (feat) {
+        const double t_i = static_cast<double>(T) / 2.0;
+        double f[kFeat];
+        f[0] = log1p(dd);
+        f[1] = log1p(static_cast<double>(S) / dd);
+        f[2] = log1p(static_cast<double>(X));
+        f[3] = log1p(d >= 2 ? 2.0 * t_i / (dd * (dd - 1.0)) : 0.0);
+        f[4] = log1p(static_cast<double>(W));
+        for (int c = 0; c < kFeat; ++c) {
+          float v = static_cast<float>(f[c]);
+          if (mean) v = (v - mean[c]) / sdev[c];
+          feat[i * kFeat + c] = v;
+        }
+      }
+      if (diag) {
+        const double t[4] = {1.0, 0.0, 2.0 * IS / dd - 1.0, 4.0 * TW / dd};
+        for (int m = 0; m < n_diag; ++m) diag[i * ld + m] = static_cast<float>(t[m]);
       }
     }
     __syncthreads();
+  }
+}
+
+// Launch of k_features: LDS bitmaps when they fit, else per-block slices of
+// a device workspace of at most kGlobalBitmapBytes (fewer blocks then).
+constexpr size_t kGlobalBitmapBytes = size_t(4) << 30;
+
+nd_status launch_features(const nd_graph* g, const float* mean, const float* sdev, float* feat, float* diag,
+                          int64_t ld, int n_diag, hipStream_t st) {
+  const int64_t n = g->n;
+  if (n == 0) return ND_OK;
+  const int64_t words = (n + 31) / 32;
+  const size_t per_block = static_cast<size_t>(2) * words * sizeof(uint32_t);
+  if (per_block <= kLdsBitmapBytes) {
+    ND_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_features<true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(per_block)));
+    const int grid = static_cast<int>(n < 4096 ? n : 4096);
+    hipLaunchKernelGGL(k_features<true>, dim3(grid), dim3(kBlock), per_block, st, g->row_ptr, g->col, n, words,
+                       static_cast<uint32_t*>(nullptr), mean, sdev, feat, diag, ld, n_diag);
+    ND_LAUNCH_CHECK();
+    return ND_OK;
+  }
+  int64_t grid = static_cast<int64_t>(kGlobalBitmapBytes / per_block);
+  if (grid > 1024) grid = 1024;
+  if (grid > n) grid = n;
+  if (grid < 1) {
+    set_error("node features: %lld nodes need %zu bytes of bitmaps per block, more than the %zu-byte workspace",
+              (long long)n, per_block, kGlobalBitmapBytes);
+    return ND_EUNSUPPORTED;
+  }
+  Tmp t;
+  uint32_t* gbm = nullptr;
+  ND_CHECK(t.get(&gbm, static_cast<size_t>(grid) * 2 * words));
+  hipLaunchKernelGGL(k_features<false>, dim3(static_cast<int>(grid)), dim3(kBlock), 0, st, g->row_ptr, g->col, n,
+                     words, gbm, mean, sdev, feat, diag, ld, n_diag);
+  ND_LAUNCH_CHECK();
+  return ND_OK;
+}
+
+// ------------------------------------------------------------------ estimator variance
+// Per-probe variance of the per-node estimates from one run's first and
+// second probe moments (ldos = mean_j v_ij, ldos_sq = mean_j v_ij^2):
+// s2_im = k/(k-1) (ldos_sq - ldos^2).  Block b sums rows [b R, (b+1) R) of
+// each column in row order; the final pass adds the blocks in order.
+constexpr int kVarBlocks = 512;
+
+__global__ __launch_bounds__(kBlock) void k_var_partial(const double* __restrict__ ld, const double* __restrict__ sq,
+                                                        int64_t n, int M, double scale, int64_t rows_per_block,
+                                                        double* __restrict__ part) {
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < n ? r0 + rows_per_block : n;
+  for (int m = threadIdx.x; m < M; m += kBlock) {
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+      const double a = ld[r * M + m];
+      s += scale * (sq[r * M + m] - a * a);
+    }
+    part[static_cast<int64_t>(blockIdx.x) * M + m] = s;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_var_final(const double* __restrict__ part, int blocks, int64_t n, int M,
+                                                      int m_lo, double* __restrict__ per_m, double* __restrict__ out) {
+  __shared__ double col[1024];
+  for (int m = threadIdx.x; m < M; m += kBlock) {
+    double s = 0.0;
+    for (int b = 0; b < blocks; ++b) s += part[static_cast<int64_t>(b) * M + m];
+    col[m] = s / static_cast<double>(n);
+    if (per_m) per_m[m] = col[m];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int m = m_lo; m < M; ++m) s += col[m];
+    out[0] = s / static_cast<double>(M - m_lo);
   }
 }
 
@@ -393,20 +529,16 @@ nd_status nd_node_features(const nd_graph* g, const float* mean, const float* st
   clear_error();
   ND_REQUIRE(g != nullptr && feat != nullptr, "nd_node_features: graph or feat is NULL");
   ND_REQUIRE((mean == nullptr) == (std == nullptr), "nd_node_features: give both mean and std, or neither");
-  if (g->n > kMaxFeatNodes) {
-    set_error("nd_node_features: %lld nodes exceed the limit of %lld", (long long)g->n, (long long)kMaxFeatNodes);
-    return ND_EUNSUPPORTED;
-  }
-  if (g->n == 0) return ND_OK;
-  const int words = static_cast<int>((g->n + 31) / 32);
-  const size_t lds = static_cast<size_t>(2) * words * sizeof(uint32_t);
-  ND_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_features), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             static_cast<int>(lds)));
-  const int grid = static_cast<int>(g->n < 65536 ? g->n : 65536);
-  hipLaunchKernelGGL(k_features, dim3(grid), dim3(kBlock), lds, as_stream(stream), g->row_ptr, g->col, g->n, words,
-                     mean, std, feat);
-  ND_LAUNCH_CHECK();
-  return ND_OK;
+  return launch_features(g, mean, std, feat, nullptr, 0, 0, as_stream(stream));
+}
+
+nd_status nd_cv_exact_diag(const nd_graph* g, float* cv_g, int64_t ld, int32_t n_cols, void* stream) {
+  using namespace nd;
+  clear_error();
+  ND_REQUIRE(g != nullptr && cv_g != nullptr, "nd_cv_exact_diag: graph or cv_g is NULL");
+  ND_REQUIRE(n_cols >= 1 && n_cols <= 4, "nd_cv_exact_diag: n_cols=%d must be 1..4", n_cols);
+  ND_REQUIRE(ld >= n_cols, "nd_cv_exact_diag: ld=%lld < n_cols=%d", (long long)ld, n_cols);
+  return launch_features(g, nullptr, nullptr, nullptr, cv_g, ld, n_cols, as_stream(stream));
 }
 
 nd_status nd_column_stats(const float* x, int64_t n_rows, int32_t n_cols, float* mean, float* std, void* stream) {
@@ -480,3 +612,41 @@ nd_status nd_adam_step(float* params, float* m, float* v, const float* grad, int
 }
 
 }  // extern "C"
+
+nd_status nd_ldos_variance(const double* ldos, const double* ldos_sq, int64_t n, int32_t n_moments, int32_t m_lo,
+                           int32_t n_probes, double* out, double* per_m, void* stream) {
+  using namespace nd;
+  clear_error();
+  ND_REQUIRE(ldos != nullptr && ldos_sq != nullptr && out != nullptr, "nd_ldos_variance: a buffer is NULL");
+  ND_REQUIRE(n >= 1, "nd_ldos_variance: n=%lld must be >= 1", (long long)n);
+  ND_REQUIRE(n_moments >= 1 && n_moments <= 1024, "nd_ldos_variance: n_moments=%d must be 1..1024", n_moments);
+  ND_REQUIRE(m_lo >= 0 && m_lo < n_moments, "nd_ldos_variance: m_lo=%d not in [0, %d)", m_lo, n_moments);
+  ND_REQUIRE(n_probes >= 2, "nd_ldos_variance: n_probes=%d must be >= 2", n_probes);
+  hipStream_t st = as_stream(stream);
+  const int64_t rpb = ceil_div(n, static_cast<int64_t>(kVarBlocks));
+  const int blocks = static_cast<int>(ceil_div(n, rpb));
+  Tmp t;
+  double* part = nullptr;
+  ND_CHECK(t.get(&part, static_cast<size_t>(blocks) * n_moments));
+  const double scale = static_cast<double>(n_probes) / (n_probes - 1.0);
+  hipLaunchKernelGGL(k_var_partial, dim3(blocks), dim3(kBlock), 0, st, ldos, ldos_sq, n, n_moments, scale, rpb, part);
+  ND_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_var_final, dim3(1), dim3(kBlock), 0, st, part, blocks, n, n_moments, m_lo, per_m, out);
+  ND_LAUNCH_CHECK();
+  return ND_OK;
+}
+
+nd_status nd_motif_diag(const nd_motifs* motifs, float* cv_g, int64_t ld, int32_t n_cols, double scale,
+                        void* stream) {
+  using namespace nd;
+  clear_error();
+  ND_REQUIRE(motifs != nullptr && cv_g != nullptr, "nd_motif_diag: motifs or cv_g is NULL");
+  ND_REQUIRE(n_cols >= 1 && ld >= n_cols, "nd_motif_diag: n_cols=%d, ld=%lld (need 1 <= n_cols <= ld)", n_cols,
+             (long long)ld);
+  if (motifs->n_classes == 0) return ND_OK;
+  hipLaunchKernelGGL(k_motif_diag<float>, dim3(grid_for(motifs->n_members, kBlock)), dim3(kBlock), 0,
+                     as_stream(stream), motifs->class_ptr, motifs->members, motifs->class_lambda,
+                     motifs->class_paired, motifs->n_classes, motifs->n_members, ld, n_cols, scale, cv_g);
+  ND_LAUNCH_CHECK();
+  return ND_OK;
+}

@@ -19,8 +19,11 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from . import (ND_PROBE_GAUSSIAN, ND_PROBE_RADEMACHER, N_FEAT, n_params, nd_adam_step, nd_column_stats,
-               nd_ldos_moments, nd_mlp_forward, nd_mlp_grad, nd_node_features)
+from . import (ND_HUBPATHS, ND_PENDANTS, ND_PROBE_GAUSSIAN, ND_PROBE_RADEMACHER, ND_TWINS_CLOSED, ND_TWINS_OPEN,
+               N_FEAT, n_params, nd_adam_step, nd_column_stats, nd_cv_exact_diag, nd_ldos_moments, nd_ldos_variance,
+               nd_mlp_forward, nd_mlp_grad, nd_motif_diag, nd_motif_filter, nd_node_features)
+
+ALL_MOTIFS = ND_TWINS_OPEN | ND_TWINS_CLOSED | ND_PENDANTS | ND_HUBPATHS
 
 F32, F64 = torch.float32, torch.float64
 
@@ -90,9 +93,40 @@ def train(graphs, targets, n_out: int, init: np.ndarray, steps: int = 2000, batc
     return cv, hist
 
 
-def predict(g, cv: ControlVariate) -> torch.Tensor:
+def motifs_of(g, seed: int = 1):
+    """Motif classes of every kind the library detects (Sec. 3.4)."""
+    return nd_motif_filter(g, seed, ALL_MOTIFS)
+
+
+def smooth_targets(targets: torch.Tensor, motifs, n_out: int) -> torch.Tensor:
+    """Training targets without the exactly known motif part of the
+    diagonal: the MLP learns the remainder (in place)."""
+    nd_motif_diag(motifs, targets, n_out, n_out, -1.0)
+    return targets
+
+
+def predict(g, cv: ControlVariate, motifs=None, exact_low: bool = True) -> torch.Tensor:
+    """The control variate g [N][n_out]: the MLP's output, plus the exact
+    motif part of the diagonal for class members (when the model was trained
+    on smooth targets, give the same kinds of motifs), with the exactly known
+    T_0..T_3(H)_ii in the first four columns (exact_low)."""
     out = torch.empty(g.n * cv.n_out, dtype=F32, device="cuda")
     nd_mlp_forward(cv.params, features(g, cv), g.n, cv.n_out, out)
+    if motifs is not None:
+        nd_motif_diag(motifs, out, cv.n_out, cv.n_out, 1.0)
+    if exact_low:
+        nd_cv_exact_diag(g, out, cv.n_out, min(4, cv.n_out))
+    return out
+
+
+def exact_known(g, n_out: int, motifs=None) -> torch.Tensor:
+    """A control variate holding only what is known exactly: T_0..T_3(H)_ii
+    and the motif part of every class member's diagonal (zero elsewhere);
+    the baseline the learned part must improve on."""
+    out = torch.zeros(g.n * n_out, dtype=F32, device="cuda")
+    if motifs is not None:
+        nd_motif_diag(motifs, out, n_out, n_out, 1.0)
+    nd_cv_exact_diag(g, out, n_out, min(4, n_out))
     return out
 
 
@@ -104,8 +138,9 @@ def probe_variance(g, n_moments: int, n_probes: int, seed: int, gaussian: bool, 
     sq = torch.empty(g.n * n_moments, dtype=F64, device="cuda")
     flags = ND_PROBE_GAUSSIAN if gaussian else ND_PROBE_RADEMACHER
     nd_ldos_moments(g, None, k, n_moments, seed, flags, ld, cv_g=cv_g, ldos_sq=sq)
-    s2 = (sq - ld * ld).reshape(g.n, n_moments)[:, 1:] * (k / (k - 1.0))
-    return float(s2.mean().item())
+    out = torch.empty(1, dtype=F64, device="cuda")
+    nd_ldos_variance(ld, sq, g.n, n_moments, 1, k, out)
+    return float(out.item())
 
 
 def empirical_variance(g, n_moments: int, n_probes: int, reps: int, seed: int, gaussian: bool, cv_g=None) -> float:

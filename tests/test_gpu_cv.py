@@ -47,6 +47,86 @@ def test_features(nd, name):
     assert np.allclose(got2, (want - mean) / std, rtol=1e-5, atol=1e-5)
 
 
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+def test_cv_exact_diag(nd, name):
+    """T_0..T_3(H)_ii from closed forms on the device against the oracle's
+    exact diagonal (the recurrence with Z = I, Sec. 3.1)."""
+    import torch
+    n, s, d = GRAPHS[name]()
+    g = nd.nd_build_csr(n, s, d)
+    g_or = og.build_csr(n, s, d)
+    _, want = kpm.exact_moments_recurrence(og.normalized_adjacency(g_or), 4)
+    ld = 7
+    out = torch.full((g.n * ld,), 3.0, dtype=torch.float32, device="cuda")
+    nd.nd_cv_exact_diag(g, out, ld, 4)
+    got = out.cpu().numpy().reshape(g.n, ld)
+    assert np.max(np.abs(got[:, :4] - want)) < 1e-6
+    assert np.all(got[:, 4:] == 3.0)                      # other columns untouched
+    assert np.all(got[:, 0] == 1.0) and np.all(got[:, 1] == 0.0)
+
+
+def test_features_beyond_lds_bitmaps(nd):
+    """A graph of more than 524288 nodes: the neighbourhood bitmaps move to a
+    device workspace; features against the oracle."""
+    import torch
+    n, s, d = sg.erdos_renyi(600_000, 5.0 / 600_000, seed=4)
+    g = nd.nd_build_csr(n, s, d)
+    assert g.n > 524288
+    g_or = og.build_csr(n, s, d)
+    want = ocv.log_scale(ocv.raw_features(g_or))
+    f = torch.empty(g.n * 5, dtype=torch.float32, device="cuda")
+    nd.nd_node_features(g, f)
+    assert np.allclose(f.cpu().numpy().reshape(g.n, 5), want, rtol=1e-6, atol=1e-6)
+    out = torch.zeros(g.n * 4, dtype=torch.float32, device="cuda")
+    nd.nd_cv_exact_diag(g, out, 4, 4)
+    t2 = kpm.cheb_moment_2_diag(g_or)
+    assert np.max(np.abs(out.cpu().numpy().reshape(g.n, 4)[:, 2] - t2)) < 1e-6
+
+
+def test_motif_diag(nd):
+    """The exact motif part of the diagonal for every kind of class, against
+    the oracle's classes, eigenvalues and Chebyshev values (Sec. 3.4)."""
+    import torch
+    from oracle import twins
+    n, s, d = sg.barabasi_albert(2000, 1, seed=4)             # a tree: open and pendant twins
+    n, s, d = sg.plant_adjacent_pairs(n, s, d, 30, seed=9)     # closed twins
+    g = nd.nd_build_csr(n, s, d)
+    g_or = og.build_csr(n, s, d)
+    kinds = nd.ND_TWINS_OPEN | nd.ND_TWINS_CLOSED | nd.ND_PENDANTS | nd.ND_HUBPATHS
+    m = nd.nd_motif_filter(g, 3, kinds)
+    cls, lam = twins.motif_classes(g_or, {"open", "closed", "pendants", "hubpaths"})
+    M, ld = 12, 15
+    want = np.full((g_or.n, ld), 0.25)
+    for c, sig in zip(cls, lam):
+        t = sum(f * twins.cheb_at(x, M) for x, f in twins.signature(sig))
+        want[np.asarray(c), :M] += -2.0 * (1.0 - 1.0 / len(c)) * t
+    out = torch.full((g.n * ld,), 0.25, dtype=torch.float32, device="cuda")
+    nd.nd_motif_diag(m, out, ld, M, -2.0)
+    assert np.max(np.abs(out.cpu().numpy().reshape(g.n, ld) - want)) < 1e-6
+
+
+def test_ldos_variance(nd):
+    """The library's variance reduction against the per-probe sample variance
+    computed from the oracle's estimates on the same probes."""
+    import torch
+    from oracle import rng as orng
+    n, s, d = GRAPHS["rmat"]()
+    g = nd.nd_build_csr(n, s, d)
+    g_or = og.build_csr(n, s, d)
+    k, M = 24, 20
+    G = np.random.default_rng(2).normal(size=(g_or.n, M)).astype(np.float32)
+    Z = orng.gaussian(g_or.n, k, 9)
+    _, C, S2 = kpm.cv_ldos(og.normalized_adjacency(g_or), Z, M, G.astype(np.float64))
+    s2 = k / (k - 1.0) * (S2 - C * C)
+    ld = _t(C, torch.float64)
+    sq = _t(S2, torch.float64)
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    per_m = torch.empty(M, dtype=torch.float64, device="cuda")
+    nd.nd_ldos_variance(ld, sq, g_or.n, M, 1, k, out, per_m)
+    assert abs(out.item() - s2[:, 1:].mean()) < 1e-12 * (1 + abs(s2[:, 1:].mean()))
+    assert np.allclose(per_m.cpu().numpy(), s2.mean(axis=0), rtol=1e-12, atol=1e-14)
+
+
 def test_column_stats(nd):
     import torch
     x = np.random.default_rng(0).normal(3.0, 2.0, size=(100_003, 5)).astype(np.float32)
