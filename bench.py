@@ -238,9 +238,10 @@ def precision_study(args) -> dict:
 
 def nested_study(args) -> dict:
     """Exact PDOS of every node by nested dissection against the stochastic
-    per-node estimate (KPM, 64 probes) on graphs with small separators: a
-    300 x 300 lattice and a preferential-attachment tree of 10^5 nodes, 100
-    moments.  Reports the partition, the time of each method, and the KPM
+    per-node estimate (KPM, 64 probes): graphs with small separators (a
+    300 x 300 lattice, a preferential-attachment tree of 10^5 nodes) and
+    without (Barabasi-Albert m = 2 and Erdos-Renyi of mean degree 6, 20,000
+    nodes each), 100 moments.  Reports the partition, the time of each method, and the KPM
     estimate's error against the exact moments."""
     import torch
     import paper_1905_09758_amd as nd
@@ -248,7 +249,9 @@ def nested_study(args) -> dict:
     M, k = 100, 64
     out = {"moments": M, "kpm_probes": k, "graphs": []}
     for name, (n, s, d) in (("lattice 300x300", sg.grid2d(300, 300)),
-                            ("BA tree n=1e5 m=1", sg.barabasi_albert(100_000, 1, seed=args.seed))):
+                            ("BA tree n=1e5 m=1", sg.barabasi_albert(100_000, 1, seed=args.seed)),
+                            ("BA n=20000 m=2", sg.barabasi_albert(20_000, 2, seed=args.seed)),
+                            ("ER n=20000 mean degree 6", sg.erdos_renyi(20_000, 6.0 / 20_000, seed=args.seed))):
         g = nd.nd_build_csr(n, s, d)
         pd = torch.empty(g.n * M, dtype=torch.float64, device="cuda")
         try:

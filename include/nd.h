@@ -303,10 +303,12 @@ nd_status nd_pdos_nodes(const nd_graph* g, const int32_t* nodes, int32_t n_nodes
  * for every tree node the columns of T_m(H) at its separator restricted to
  * its partition, by the block recurrence with the couplings through the
  * ancestors' separators; the diagonals give T_m(H)_vv for all v.
- * The tree comes from recursive bisection on BFS level structures
- * (separators are BFS levels; components split with an empty separator),
- * stopping at partitions of at most leaf_size nodes.  Block entries are
- * fp64.
+ * The tree comes from recursive bisection (components split with an empty
+ * separator; a connected partition takes the smaller of a BFS-level
+ * separator and a multilevel one: heavy-edge coarsening, greedy growing,
+ * Fiduccia-Mattheyses refinement, minimum vertex cover of the cut edges),
+ * stopping at partitions of at most leaf_size nodes; see nd_nested_tree.
+ * Block entries are fp64.
  *   n_moments    >= 1
  *   leaf_size    1..4096
  *   max_entries  cap on the total block entries sum_t |I_p| |I_s| (two fp64
@@ -320,6 +322,20 @@ nd_status nd_pdos_nodes(const nd_graph* g, const int32_t* nodes, int32_t n_nodes
  * block entries than max_entries). */
 nd_status nd_pdos_nested(const nd_graph* g, int32_t n_moments, int32_t leaf_size, int64_t max_entries,
                          uint32_t flags, double* pdos, int64_t* stats, void* stream);
+
+/* The nested-dissection tree of nd_pdos_nested on the host, for inspection
+ * (Sec. 3.3, Algorithm 1's partition step; no device work).
+ *   row_ptr, col  host CSR of a symmetric graph without self loops, n nodes
+ *   owner    host int32 [n] or NULL: the tree node whose separator (or leaf)
+ *            holds each node
+ *   parent   host int32 [2n] or NULL: parent[t] of every tree node t
+ *            (-1 for the root); tree nodes number fewer than 2n
+ *   stats    host int64 [4] or NULL: as nd_pdos_nested
+ * Every edge joins two nodes whose owners lie on one root-to-leaf path.
+ * Errors: ND_EINVAL (arguments), ND_EUNSUPPORTED (a partition over 4096
+ * nodes that no separator splits). */
+nd_status nd_nested_tree(const int64_t* row_ptr, const int32_t* col, int64_t n, int32_t leaf_size,
+                         int32_t* owner, int32_t* parent, int64_t* stats);
 
 /* --------------------------------------------------------------- GQL */
 

@@ -39,7 +39,7 @@ EXPORTS = (
     "nd_graph_free",
     "nd_motif_filter", "nd_motif_info", "nd_motif_export", "nd_motif_export_lambda", "nd_motifs_free",
     "nd_make_probes",
-    "nd_cheb_moments", "nd_cheb_moments_noalloc", "nd_ldos_moments", "nd_pdos_nodes", "nd_pdos_nested", "nd_gql", "nd_gql_pdos", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_cv_exact_diag", "nd_motif_diag", "nd_ldos_variance", "nd_column_stats",
+    "nd_cheb_moments", "nd_cheb_moments_noalloc", "nd_ldos_moments", "nd_pdos_nodes", "nd_pdos_nested", "nd_nested_tree", "nd_gql", "nd_gql_pdos", "nd_gql_density", "nd_reconstruct", "nd_node_features", "nd_cv_exact_diag", "nd_motif_diag", "nd_ldos_variance", "nd_column_stats",
     "nd_mlp_forward", "nd_mlp_grad", "nd_adam_step", "nd_last_error",
 )
 
@@ -87,6 +87,7 @@ _sig("nd_cheb_moments_noalloc", [_vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp])
 _sig("nd_ldos_moments", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp, _vp])
 _sig("nd_pdos_nodes", [_vp, _vp, _i32, _i32, _u32, _vp, _vp])
 _sig("nd_pdos_nested", [_vp, _i32, _i32, _i64, _u32, _vp, _vp, _vp])
+_sig("nd_nested_tree", [_vp, _vp, _i64, _i32, _vp, _vp, _vp])
 _sig("nd_gql", [_vp, _vp, _i32, _i32, _u64, _u32, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("nd_gql_pdos", [_vp, _vp, _i32, _i32, _u32, _vp, _vp, _vp, _vp])
 _sig("nd_gql_density", [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _dbl, _dbl, _vp, _vp])
@@ -323,6 +324,24 @@ def nd_pdos_nested(g: Graph, n_moments: int, pdos, leaf_size: int = 64, max_entr
     _check(_lib.nd_pdos_nested(g.handle, n_moments, leaf_size, max_entries, flags, pp, st.ctypes.data,
                                _stream(stream)), "nd_pdos_nested")
     return {"tree_nodes": int(st[0]), "depth": int(st[1]), "separator_nodes": int(st[2]), "block_entries": int(st[3])}
+
+
+def nd_nested_tree(row_ptr, col, n: int, leaf_size: int = 64) -> dict:
+    """The nested-dissection tree of a host CSR graph (no device work):
+    owner [n] (tree node of each node's separator), parent [tree nodes] and
+    the partition statistics."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    if rp.size != n + 1 or cl.size != int(rp[-1]):
+        raise ValueError("row_ptr / col sizes do not match n")
+    owner = np.full(n, -1, np.int32)
+    parent = np.full(2 * n, -2, np.int32)
+    st = np.zeros(4, np.int64)
+    _check(_lib.nd_nested_tree(rp.ctypes.data, cl.ctypes.data if cl.size else None, n, leaf_size,
+                               owner.ctypes.data, parent.ctypes.data, st.ctypes.data), "nd_nested_tree")
+    T = int(st[0])
+    return {"owner": owner, "parent": parent[:T].copy(), "tree_nodes": T, "depth": int(st[1]),
+            "separator_nodes": int(st[2]), "block_entries": int(st[3])}
 
 
 def nd_gql(g: Graph, motifs, n_probes: int, n_steps: int, seed: int, flags: int, nodes, weights, steps=None,

@@ -19,3 +19,10 @@ def nd():
     import paper_1905_09758_amd as lib
     lib.require_gpu()
     return lib
+
+
+@pytest.fixture(scope="session")
+def nd_host():
+    """The HIP library binding for its host-only entry points (no device)."""
+    import paper_1905_09758_amd as lib
+    return lib

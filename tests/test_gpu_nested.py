@@ -1,8 +1,9 @@
 """Nested dissection PDOS (Sec. 3.3, Algorithm 1) on the GPU against the
 exact PDOS moments of the oracle's eigendecomposition (needs an MI355X).
-Graphs with small separators (lattices, trees, rings, paths), disconnected
-graphs (empty separators), graphs that stay one dense leaf, and the clean
-refusal when the blocks would be too large."""
+Graphs with small separators (lattices, trees, rings, paths), graphs
+without BFS-level separators (Erdos-Renyi, Barabasi-Albert: multilevel
+bisection), disconnected graphs (empty separators), graphs that stay one
+dense leaf, and the clean refusal when the blocks would be too large."""
 import numpy as np
 import pytest
 
@@ -29,6 +30,9 @@ GRAPHS = {
     "star": (lambda: sg.star(150), 32),
     "complete": (lambda: sg.complete(30), 64),
     "er": (lambda: sg.erdos_renyi(300, 0.02, seed=5), 64),
+    # no BFS-level separators: split by the multilevel bisection
+    "er3000": (lambda: sg.erdos_renyi(3000, 0.004, seed=7), 64),
+    "ba3000": (lambda: sg.barabasi_albert(3000, 3, seed=4), 64),
 }
 
 
@@ -50,6 +54,20 @@ def test_nested_dissection_pdos_exact(nd, name):
         assert st["depth"] >= 2, st
     if name in ("grid", "path", "ring"):
         assert st["separator_nodes"] < g.n // 4, st
+
+
+def test_nested_dissection_tree_matches_device_call(nd):
+    """The statistics nd_pdos_nested reports are those of the host tree
+    that nd_nested_tree builds for the same graph and leaf size."""
+    import torch
+    n, s, d = sg.barabasi_albert(3000, 3, seed=4)
+    g_or = og.build_csr(n, s, d)
+    g = nd.nd_build_csr(n, s, d)
+    pd = torch.zeros(g.n * 3, dtype=torch.float64, device="cuda")
+    st = nd.nd_pdos_nested(g, 3, pd, leaf_size=64)
+    t = nd.nd_nested_tree(g_or.row_ptr, g_or.col, g_or.n, 64)
+    for k in ("tree_nodes", "depth", "separator_nodes", "block_entries"):
+        assert st[k] == t[k], (k, st, t)
 
 
 def test_nested_dissection_refuses_large_blocks(nd):
