@@ -105,6 +105,30 @@ def test_motif_diag(nd):
     assert np.max(np.abs(out.cpu().numpy().reshape(g.n, ld) - want)) < 1e-6
 
 
+def test_control_variate_with_twin_classes_is_refused(nd):
+    """A projected probe entry of a class member has mean square 1/|C|, not 1,
+    so g (1 - z~_i^2) would bias that row: cv_g together with motifs that
+    hold classes is refused; motifs without classes are accepted."""
+    import torch
+    n, s, d = GRAPHS["ba_twins"]()
+    g = nd.nd_build_csr(n, s, d)
+    m = nd.nd_motif_filter(g, 1)
+    assert m.n_classes > 0
+    M, k = 8, 4
+    cvg = torch.zeros(g.n * M, dtype=torch.float32, device="cuda")
+    ld = torch.zeros(g.n * M, dtype=torch.float64, device="cuda")
+    with pytest.raises(nd.NDError) as e:
+        nd.nd_ldos_moments(g, m, k, M, 3, nd.ND_PROBE_GAUSSIAN, ld, cv_g=cvg)
+    assert e.value.status == nd.ND_EINVAL
+    n2, s2, d2 = sg.cycle(50)                       # no twins: an empty class list
+    g2 = nd.nd_build_csr(n2, s2, d2)
+    m2 = nd.nd_motif_filter(g2, 1)
+    assert m2.n_classes == 0
+    cv2 = torch.zeros(g2.n * M, dtype=torch.float32, device="cuda")
+    ld2 = torch.zeros(g2.n * M, dtype=torch.float64, device="cuda")
+    nd.nd_ldos_moments(g2, m2, k, M, 3, nd.ND_PROBE_GAUSSIAN, ld2, cv_g=cv2)
+
+
 def test_ldos_variance(nd):
     """The library's variance reduction against the per-probe sample variance
     computed from the oracle's estimates on the same probes."""

@@ -575,6 +575,27 @@ def test_reconstruct(nd):
             assert np.max(np.abs(rho.cpu().numpy().reshape(rows.shape[0], 64) - r_o)) < 1e-9
 
 
+def test_reconstruct_table_exactly_one_size_class(nd):
+    """A table whose column tiles end exactly at its allocation (M <= 32,
+    50 bins fused into the product plus 65 density points): the last column
+    tile must not read past the table (columns past the launch's count load
+    0), and the results match the oracle."""
+    import torch
+    n, s, d = sg.erdos_renyi(300, 0.02, seed=6)
+    g_or = og.build_csr(n, s, d)
+    M, nb, K = 32, 62, 65
+    mu, ldos = kpm.exact_moments_eig(og.normalized_adjacency(g_or), M)
+    rows = 70
+    mom = np.vstack([mu[None, :], ldos[:rows - 1]])
+    hist = _zeros(rows * nb, torch.float64)
+    rho = _zeros(rows * K, torch.float64)
+    nd.nd_reconstruct(_t(mom), rows, M, nd.ND_KERNEL_JACKSON, (), nb, -1.0, 1.0, hist, K, rho)
+    h_o = rc.histogram(mom, nb, -1.0, 1.0, kernel="jackson")
+    assert np.max(np.abs(hist.cpu().numpy().reshape(rows, nb) - h_o).sum(axis=1)) < 1e-10
+    r_o = rc.density(mom, rc.cheb_nodes(K), kernel="jackson")
+    assert np.max(np.abs(rho.cpu().numpy().reshape(rows, K) - r_o)) < 1e-9
+
+
 @pytest.mark.parametrize("nb", [50, 63, 64])
 def test_reconstruct_tiles_and_spikes_in_moments(nd, nb):
     """Several row tiles with a ragged last one, a moment count that is not a
