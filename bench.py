@@ -550,21 +550,27 @@ def main():
         nd.nd_reconstruct(out["mu"], 1, M, kern, spikes, W.bins, -1.0, 1.0, out["hist"])
         return g, motifs
 
-    for _ in range(args.warmup):
+    def progress(msg):
+        print("bench: " + msg, file=sys.stderr, flush=True)
+
+    progress("%s: input generated in %.1f s (%d nodes, %d edges)" % (args.workload, t_gen, n_nodes, src_d.numel()))
+    for i in range(args.warmup):
         g, motifs = step(False)
         del g, motifs
+        progress("warm-up step %d/%d done" % (i + 1, args.warmup))
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     kern_ms, kern_n = 0.0, 0
     t0 = time.perf_counter()
     ev0.record()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         g, motifs = step(True)
         ms, nl = nd.nd_graph_step_timing(g)
         kern_ms += ms
         kern_n += nl
         info = (g.n, g.nnz, g.max_deg, motifs.n_classes if motifs is not None else 0)
         del g, motifs
+        progress("timed step %d/%d done" % (i + 1, args.steps))
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
