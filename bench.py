@@ -236,6 +236,69 @@ def precision_study(args) -> dict:
     return out
 
 
+def methods_study(args) -> dict:
+    """The three global-DOS methods of the library on the precision-study
+    graph (R-MAT scale 22 ef 16, 32 probes, 1000 moments), in fp32 and fp64
+    state, against the fp64 oracle's stored moments and 200-bin density
+    (tests/golden/rmat22_oracle.npz): KPM (999 sparse products per probe),
+    the doubling identities (500 products), and Gauss quadrature by Lanczos
+    with K = 500 steps, whose rule reproduces the Chebyshev moments up to
+    degree 2K - 1 = 999 (Sec. 3.1, Sec. 3.2)."""
+    import torch
+    import paper_1905_09758_amd as nd
+    from synthgraph.workloads import WORKLOADS
+    W = WORKLOADS["rmat22"]
+    k, M, bins = W.probes, W.moments, W.bins
+    K = M // 2
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "rmat22_oracle.npz"), allow_pickle=False)
+    n_nodes, src, dst = W.graph(args.seed)
+    g = nd.nd_build_csr(n_nodes, torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda())
+    del src, dst
+    if int(gold["n"]) != g.n or int(gold["nnz"]) != g.nnz or int(gold["probe_seed"]) != args.seed:
+        raise SystemExit("methods study: the stored oracle values are for another graph or seed")
+    mu_o = gold["mu_pp"].mean(axis=0)
+    f64 = torch.float64
+    out = {"workload": "rmat22", "graph": W.describe, "n": g.n, "nnz": g.nnz, "probes": k, "moments": M,
+           "gql_steps": K, "methods": []}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for state, sflag in (("fp32", 0), ("fp64", nd.ND_STATE_FP64)):
+        for method in ("kpm", "doubling", "gql"):
+            mu = torch.empty(M, dtype=f64, device="cuda")
+            nodes = weights = None
+
+            def run():
+                nonlocal nodes, weights
+                if method == "gql":
+                    nodes = torch.empty(k * K, dtype=f64, device="cuda")
+                    weights = torch.empty(k * K, dtype=f64, device="cuda")
+                    nd.nd_gql(g, None, k, K, args.seed, sflag, nodes, weights)
+                    nd.nd_gql_density(nodes, weights, k, K, M, mu)
+                else:
+                    fl = sflag | (nd.ND_MOMENT_DOUBLING if method == "doubling" else 0)
+                    nd.nd_cheb_moments(g, None, k, M, args.seed, fl, mu)
+
+            run()                                  # warm-up (schedules, workspaces)
+            torch.cuda.synchronize()
+            ev0.record()
+            run()
+            ev1.record()
+            torch.cuda.synchronize()
+            hist = torch.empty(bins, dtype=f64, device="cuda")
+            nd.nd_reconstruct(mu, 1, M, nd.ND_KERNEL_JACKSON, (), bins, -1.0, 1.0, hist)
+            e = np.abs(mu.cpu().numpy() - mu_o)
+            out["methods"].append({
+                "method": method, "state": state,
+                "sparse_products_per_probe": {"kpm": M - 1, "doubling": M // 2, "gql": K}[method],
+                "ms": round(ev0.elapsed_time(ev1), 2),
+                "global_max_abs_err_m<=200": float(e[:201].max()),
+                "global_max_abs_err": float(e.max()),
+                "global_err_at": {str(i): float(e[i]) for i in (1, 10, 100, 200, 500, 800, 999)},
+                "density_L1_200bins": float(np.abs(hist.cpu().numpy() - gold["hist200"]).sum()),
+            })
+            print("methods study: %s %s done" % (method, state), file=sys.stderr, flush=True)
+    return out
+
+
 def nested_study(args) -> dict:
     """Exact PDOS of every node by nested dissection against the stochastic
     per-node estimate (KPM, 64 probes): graphs with small separators (a
@@ -462,6 +525,8 @@ def main():
     ap.add_argument("--doubling", action="store_true",
                     help="global-DOS workloads: moments from floor(M/2) sparse products (doubling identities); "
                          "the rate still counts the products actually done")
+    ap.add_argument("--methods-study", action="store_true",
+                    help="KPM, doubling and GQL on R-MAT scale 22 against the fp64 oracle's stored moments")
     ap.add_argument("--nested-study", action="store_true",
                     help="exact PDOS by nested dissection vs 64-probe KPM on a lattice and a tree")
     ap.add_argument("--motif-study", action="store_true",
@@ -501,6 +566,9 @@ def main():
         return
     if args.nested_study:
         print(json.dumps(nested_study(args)), flush=True)
+        return
+    if args.methods_study:
+        print(json.dumps(methods_study(args)), flush=True)
         return
     if args.motif_study:
         print(json.dumps(motif_study(args)), flush=True)
