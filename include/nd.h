@@ -316,10 +316,12 @@ nd_status nd_pdos_nodes(const nd_graph* g, const int32_t* nodes, int32_t n_nodes
  *   flags        optionally ND_TIME_STEPS (per-moment launches)
  *   pdos         device double [N][n_moments], row-major
  *   stats        host int64 [4] or NULL: tree nodes, depth, separator
- *                nodes, block entries
+ *                nodes, block entries (left unset when the call fails)
  * Synchronises `stream`.  ND_EUNSUPPORTED when the graph has no small
- * separators (a partition over 4096 nodes without a separator, or more
- * block entries than max_entries). */
+ * separators: a partition over 4096 nodes without a separator, or more
+ * block entries than max_entries (the tree build stops as soon as its
+ * running count passes the cap; partitions over 4 M nodes are split by
+ * BFS levels only). */
 nd_status nd_pdos_nested(const nd_graph* g, int32_t n_moments, int32_t leaf_size, int64_t max_entries,
                          uint32_t flags, double* pdos, int64_t* stats, void* stream);
 

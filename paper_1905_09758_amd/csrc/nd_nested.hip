@@ -501,10 +501,24 @@ bool bfs_separator(const std::vector<int64_t>& rp, const std::vector<int32_t>& c
   return !left.empty() && !right.empty();
 }
 
+// Partitions larger than this are split by BFS levels only (the multilevel
+// bisection's coarsening copies the partition's subgraph several times).
+constexpr size_t kMaxMultilevel = size_t(1) << 22;
+
 // Builds the tree.  Returns false (message set) when a partition that cannot
-// be split stays larger than max_leaf.
+// be split stays larger than max_leaf, or as soon as the blocks exceed
+// max_entries entries.
 bool build_tree(const std::vector<int64_t>& rp, const std::vector<int32_t>& col, int64_t n, int leaf_size,
-                int max_leaf, std::vector<TreeNode>& tree) {
+                int max_leaf, int64_t max_entries, std::vector<TreeNode>& tree) {
+  int64_t entries = 0;
+  auto add_entries = [&](size_t part, size_t sep) {
+    entries += static_cast<int64_t>(part) * static_cast<int64_t>(sep);
+    if (entries > max_entries) {
+      set_error("nd_pdos_nested: the blocks need more than max_entries=%lld entries", (long long)max_entries);
+      return false;
+    }
+    return true;
+  };
   std::vector<int32_t> mark(static_cast<size_t>(n), -1), dist(static_cast<size_t>(n), -1), order;
   std::vector<int32_t> lid(static_cast<size_t>(n), -1);
   struct Job {
@@ -535,6 +549,7 @@ bool build_tree(const std::vector<int64_t>& rp, const std::vector<int32_t>& col,
     const size_t np = P.size();
     if (static_cast<int64_t>(np) <= leaf_size) {
       tree[id].sep = P;
+      if (!add_entries(np, np)) return false;
       continue;
     }
     for (int32_t v : P) {
@@ -558,7 +573,7 @@ bool build_tree(const std::vector<int64_t>& rp, const std::vector<int32_t>& col,
     // within 2 sqrt(|P|) (the size planar-like graphs admit) is taken as is.
     const bool ok_a = bfs_separator(rp, col, mark, id, P, dist, order, sa, la, ra);
     const bool small_a = ok_a && static_cast<double>(sa.size()) <= 2.0 * std::sqrt(static_cast<double>(np));
-    const bool ok_b = !small_a && multilevel_separator(rp, col, mark, id, P, lid, sb, lb, rb);
+    const bool ok_b = !small_a && np <= kMaxMultilevel && multilevel_separator(rp, col, mark, id, P, lid, sb, lb, rb);
     if (!ok_a && !ok_b) {
       if (static_cast<int64_t>(np) > max_leaf) {
         set_error("nd_pdos_nested: a partition of %zu nodes has no separator that splits it; the graph has no "
@@ -566,6 +581,7 @@ bool build_tree(const std::vector<int64_t>& rp, const std::vector<int32_t>& col,
         return false;
       }
       tree[id].sep = P;
+      if (!add_entries(np, np)) return false;
       continue;
     }
     const bool use_b = ok_b && (!ok_a || sb.size() < sa.size());
@@ -574,6 +590,7 @@ bool build_tree(const std::vector<int64_t>& rp, const std::vector<int32_t>& col,
     std::vector<int32_t>& right = use_b ? rb : ra;
     tree[id].sep = sep;
     std::sort(tree[id].sep.begin(), tree[id].sep.end());
+    if (!add_entries(np, sep.size())) return false;
     stack.push_back({left, job.depth + 1, id});
     stack.push_back({right, job.depth + 1, id});
   }
@@ -688,7 +705,7 @@ extern "C" nd_status nd_pdos_nested(const nd_graph* g, int32_t n_moments, int32_
   std::vector<TreeNode> tree;
   // a partition that cannot be split may stay dense up to this size
   const int max_leaf = 4096;
-  if (!build_tree(rp, col, n, leaf_size, max_leaf, tree)) return ND_EUNSUPPORTED;
+  if (!build_tree(rp, col, n, leaf_size, max_leaf, max_entries, tree)) return ND_EUNSUPPORTED;
   const int64_t T = static_cast<int64_t>(tree.size());
   int max_depth = 0;
   int64_t E = 0, sep_total = 0;
@@ -819,7 +836,7 @@ extern "C" nd_status nd_nested_tree(const int64_t* row_ptr, const int32_t* col, 
   std::vector<int64_t> rp(row_ptr, row_ptr + n + 1);
   std::vector<int32_t> cl(col, col + nnz);
   std::vector<TreeNode> tree;
-  if (!build_tree(rp, cl, n, leaf_size, 4096, tree)) return ND_EUNSUPPORTED;
+  if (!build_tree(rp, cl, n, leaf_size, 4096, std::numeric_limits<int64_t>::max(), tree)) return ND_EUNSUPPORTED;
   int max_depth = 0;
   int64_t E = 0, sep_total = 0;
   for (size_t t = 0; t < tree.size(); ++t) {
