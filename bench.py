@@ -299,6 +299,51 @@ def methods_study(args) -> dict:
     return out
 
 
+def scaling_study(args) -> dict:
+    """The paper's cost model (Sec. 5): time per moment proportional to
+    N_z (|V| + |E|), and independent of the number of moments.  Per-moment
+    GPU time (average sparse-step launch, finisher included, HIP events) on
+    R-MAT graphs (ef 8, same a,b,c,d) of scale 18 to 27 at 16 probes; probe
+    counts 4 to 64 at scale 24; moment counts 20 to 400 at scale 22."""
+    import torch
+    import paper_1905_09758_amd as nd
+    import synthgraph as sg
+    f64 = torch.float64
+    out = {"graph_family": "R-MAT ef 8 (0.57, 0.19, 0.19, 0.05)", "by_scale": [], "by_probes": [], "by_moments": []}
+
+    def measure(g, k, M):
+        mu = torch.empty(M, dtype=f64, device="cuda")
+        nd.nd_cheb_moments(g, None, k, M, args.seed, 0, mu)            # warm-up (schedule)
+        nd.nd_cheb_moments(g, None, k, M, args.seed, nd.ND_TIME_STEPS, mu)
+        ms, nl = nd.nd_graph_step_timing(g)
+        per = ms / max(nl, 1)
+        work = k * (g.n + g.nnz / 2)                  # N_z (|V| + |E|), |E| undirected
+        return {"n": g.n, "nnz": g.nnz, "probes": k, "moments": M, "ms_per_moment": round(per, 4),
+                "ns_per_probe_node_plus_edge": round(per * 1e6 / work, 4),
+                "G_nnz_probe_per_s": round(g.nnz * k / (per * 1e-3) / 1e9, 1)}
+
+    graphs = {}
+    for scale in (18, 20, 22, 24, 26, 27):
+        n, s, d = sg.rmat(scale, 8, seed=args.seed)
+        g = nd.nd_build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+        del s, d
+        r = measure(g, 16, 40)
+        r["scale"] = scale
+        out["by_scale"].append(r)
+        if scale in (22, 24):
+            graphs[scale] = g
+        else:
+            del g
+        torch.cuda.empty_cache()
+        print("scaling study: scale %d done" % scale, file=sys.stderr, flush=True)
+    for k in (4, 8, 16, 32, 64):
+        out["by_probes"].append(measure(graphs[24], k, 40))
+    print("scaling study: probes done", file=sys.stderr, flush=True)
+    for M in (20, 100, 400):
+        out["by_moments"].append(measure(graphs[22], 16, M))
+    return out
+
+
 def nested_study(args) -> dict:
     """Exact PDOS of every node by nested dissection against the stochastic
     per-node estimate (KPM, 64 probes): graphs with small separators (a
@@ -525,6 +570,8 @@ def main():
     ap.add_argument("--doubling", action="store_true",
                     help="global-DOS workloads: moments from floor(M/2) sparse products (doubling identities); "
                          "the rate still counts the products actually done")
+    ap.add_argument("--scaling-study", action="store_true",
+                    help="per-moment time against N_z (|V| + |E|) on R-MAT graphs of scale 18 to 27")
     ap.add_argument("--methods-study", action="store_true",
                     help="KPM, doubling and GQL on R-MAT scale 22 against the fp64 oracle's stored moments")
     ap.add_argument("--nested-study", action="store_true",
@@ -569,6 +616,9 @@ def main():
         return
     if args.methods_study:
         print(json.dumps(methods_study(args)), flush=True)
+        return
+    if args.scaling_study:
+        print(json.dumps(scaling_study(args)), flush=True)
         return
     if args.motif_study:
         print(json.dumps(motif_study(args)), flush=True)
