@@ -829,6 +829,9 @@ extern "C" nd_status nd_nested_tree(const int64_t* row_ptr, const int32_t* col, 
   clear_error();
   ND_REQUIRE(row_ptr != nullptr && n >= 1, "nd_nested_tree: empty graph");
   ND_REQUIRE(leaf_size >= 1 && leaf_size <= 4096, "nd_nested_tree: leaf_size=%d not in [1, 4096]", leaf_size);
+  ND_REQUIRE(row_ptr[0] == 0, "nd_nested_tree: row_ptr[0] = %lld, expected 0", (long long)row_ptr[0]);
+  for (int64_t v = 0; v < n; ++v)
+    ND_REQUIRE(row_ptr[v + 1] >= row_ptr[v], "nd_nested_tree: row_ptr decreases at row %lld", (long long)v);
   const int64_t nnz = row_ptr[n];
   ND_REQUIRE(nnz == 0 || col != nullptr, "nd_nested_tree: col is NULL");
   for (int64_t e = 0; e < nnz; ++e)

@@ -95,3 +95,7 @@ def test_nested_tree_errors(nd_host):
     bad[0] = 99
     with pytest.raises(nd.NDError):
         nd.nd_nested_tree(g.row_ptr, bad, g.n, 4)
+    rp = g.row_ptr.copy()
+    rp[3], rp[4] = rp[4], rp[3]
+    with pytest.raises(nd.NDError):
+        nd.nd_nested_tree(rp, g.col, g.n, 4)
