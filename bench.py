@@ -564,6 +564,9 @@ def main():
     ap.add_argument("--cv-target-probes", type=int, default=1024)
     ap.add_argument("--cv-steps", type=int, default=3000)
     ap.add_argument("--no-filter", action="store_true", help="skip twin filtering (ba1m_twins)")
+    ap.add_argument("--ldos", action="store_true",
+                    help="global-DOS workloads: per-node moments too (the [N][M] fp64 matrix and 50-bin "
+                         "per-node histograms)")
     ap.add_argument("--gql", type=int, default=0, metavar="K",
                     help="global-DOS workloads: Gauss quadrature and Lanczos with K steps instead of KPM "
                          "(the rule's Chebyshev moments feed the same reconstruction)")
@@ -624,6 +627,9 @@ def main():
         print(json.dumps(motif_study(args)), flush=True)
         return
     W = WORKLOADS[args.workload]
+    if args.ldos and not W.ldos:
+        import dataclasses
+        W = dataclasses.replace(W, ldos=True, describe=W.describe + " + per-node LDOS")
     k, M = W.probes, W.moments
     use_filter = W.filter_twins and not args.no_filter
     t_gen = time.perf_counter()
@@ -703,8 +709,10 @@ def main():
     b_launch = algorithmic_bytes(n, nnz, k, W.ldos, own_row=bool(not W.ldos and (args.doubling or args.gql)),
                                  filtered=use_filter)
     achieved = b_launch / (avg_launch_ms * 1e-3) / 1e9
-    # the counter records are of the plain Chebyshev step launches
-    traffic = profiled_traffic(args.workload) if not (args.doubling or args.gql) else None
+    # the counter records are of the step launches of each workload's own
+    # configuration (no doubling, Lanczos, forced LDOS or disabled filter)
+    traffic = profiled_traffic(args.workload) if not (args.doubling or args.gql or args.ldos or args.no_filter) \
+        else None
     copy_gbs = copy_bandwidth_gbs()
     mu = out["mu"].cpu().numpy()
     line = {
