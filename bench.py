@@ -748,6 +748,15 @@ def main():
         "wall_s": round(wall, 3),
         "input_gen_s": round(t_gen, 2),
     }
+    if args.workload == "rmat27":
+        # the paper's own billion-edge single-node timing (its timing table), quoted as context:
+        # Friendster, 65,608,366 nodes and 1,806,067,135 undirected edges, 20 probes, average time
+        # per moment over the first 10 moments
+        line["paper_context"] = {"graph": "Friendster (65.6 M nodes, 1.81 B undirected edges)", "probes": 20,
+                                 "s_per_moment": 1017.0,
+                                 "G_nnz_probe_moment_per_s": round(2 * 1806067135 * 20 / 1017.0 / 1e9, 3),
+                                 "hardware": "one node, Intel Xeon E5 v3 at 2.3 GHz, Python (threads not stated)",
+                                 "this_run_s_per_moment": round(ms_step / 1e3 / max(products, 1), 4)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, k, W.ldos, args.seed)
     print(json.dumps(line), flush=True)
