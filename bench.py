@@ -344,6 +344,39 @@ def scaling_study(args) -> dict:
     return out
 
 
+def shard_study(args) -> dict:
+    """One GPU's share of the R-MAT scale-27 step under probe sharding: with
+    the 16 probes dealt over G GPUs, each GPU runs the whole graph with 16/G
+    probes (G = 1, 2, 4, 8).  Per-moment GPU time of the sparse step (HIP
+    events, finisher included), 40 moments, fp32 state, global moments; the
+    job's time per moment is that of one share, since the shares need no
+    exchange during the recurrence."""
+    import torch
+    import paper_1905_09758_amd as nd
+    from synthgraph.workloads import WORKLOADS
+    f64 = torch.float64
+    W = WORKLOADS["rmat27"]
+    n_nodes, s, d = W.graph(args.seed)
+    g = nd.nd_build_csr(n_nodes, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    del s, d
+    M = 40
+    out = {"graph": W.describe, "n": g.n, "nnz": g.nnz, "moments": M, "by_gpus": []}
+    base = None
+    for G in (1, 2, 4, 8):
+        k = W.probes // G
+        mu = torch.empty(M, dtype=f64, device="cuda")
+        nd.nd_cheb_moments(g, None, k, M, args.seed, 0, mu)            # warm-up (schedule)
+        nd.nd_cheb_moments(g, None, k, M, args.seed, nd.ND_TIME_STEPS, mu)
+        ms, nl = nd.nd_graph_step_timing(g)
+        per = ms / max(nl, 1)
+        base = per if base is None else base
+        out["by_gpus"].append({"gpus": G, "probes_per_gpu": k, "ms_per_moment": round(per, 3),
+                               "speedup_over_one_gpu": round(base / per, 2),
+                               "G_nnz_probe_per_s_per_gpu": round(g.nnz * k / (per * 1e-3) / 1e9, 1)})
+        print("shard study: %d probes done" % k, file=sys.stderr, flush=True)
+    return out
+
+
 def nested_study(args) -> dict:
     """Exact PDOS of every node by nested dissection against the stochastic
     per-node estimate (KPM, 64 probes): graphs with small separators (a
@@ -575,6 +608,8 @@ def main():
                          "the rate still counts the products actually done")
     ap.add_argument("--scaling-study", action="store_true",
                     help="per-moment time against N_z (|V| + |E|) on R-MAT graphs of scale 18 to 27")
+    ap.add_argument("--shard-study", action="store_true",
+                    help="one GPU's share of the R-MAT scale-27 step when the 16 probes are split over 1-8 GPUs")
     ap.add_argument("--methods-study", action="store_true",
                     help="KPM, doubling and GQL on R-MAT scale 22 against the fp64 oracle's stored moments")
     ap.add_argument("--nested-study", action="store_true",
@@ -592,8 +627,8 @@ def main():
     if args.gql and args.doubling:
         ap.error("--gql and --doubling are exclusive")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: the library runs on one GPU (sharding the probe blocks across GPUs is not "
-              "implemented); --gpus must be 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU (sharding across GPUs is not implemented; "
+              "--shard-study measures one GPU's share); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -622,6 +657,9 @@ def main():
         return
     if args.scaling_study:
         print(json.dumps(scaling_study(args)), flush=True)
+        return
+    if args.shard_study:
+        print(json.dumps(shard_study(args)), flush=True)
         return
     if args.motif_study:
         print(json.dumps(motif_study(args)), flush=True)
