@@ -234,3 +234,53 @@ def test_gql_breakdown_and_histogram():
     rules = gql.gql_probes(H, orng.rademacher(4, 3, 1), 10)
     h = gql.gql_histogram(rules, 4)
     assert abs(h.sum() - 1.0) < 1e-12
+
+
+def test_probe_estimate_is_the_eigenweight_measure():
+    """Sec. 4, error analysis: a probe z turns the spectral measure into
+    sum_i w_i^2 delta(lambda - lambda_i) with w = Q^T z, so the oracle's
+    per-probe moments must be that measure's Chebyshev moments (per sample,
+    not only in expectation), each moment's error is at most
+    (1/N) sum_i |1 - w_i^2|, and the per-node estimate is the same sum with
+    the node's eigenvector entries.  T_m(lambda_i) comes from numpy's
+    Chebyshev Vandermonde matrix, not from the oracle."""
+    g, H = H_of(sg.barabasi_albert(300, 3, seed=5))
+    lam, Q = np.linalg.eigh(H.toarray())
+    M, k = 40, 8
+    V = np.polynomial.chebyshev.chebvander(lam, M - 1)          # [N][M], T_m(lambda_i)
+    exact = V.mean(axis=0)
+    for kind in ("rademacher", "gaussian"):
+        Z = orng.probes(g.n, k, 21, kind)
+        _, pp, C = kpm.stochastic_moments(H, Z, M)
+        W = Q.T @ Z                                               # [N][k] eigen-weights
+        assert np.allclose(pp, (W * W).T @ V / g.n, rtol=0, atol=1e-11)
+        Y = np.einsum("ai,im,ij->maj", Q, V, W)                   # T_m(H) z_j from the eigenbasis
+        assert np.allclose(C, (Z[None] * Y).mean(axis=2).T, rtol=0, atol=1e-11)
+        bound = np.abs(1.0 - W * W).sum(axis=0) / g.n             # per probe
+        assert np.all(np.abs(pp - exact[None]) <= bound[:, None] + 1e-12)
+
+
+def test_probe_weight_error_follows_chi_square():
+    """Sec. 4, error analysis: with N_z standard-normal probes, N_z times the
+    mean squared weight on an eigenvector is chi^2(N_z), so E|1 - w^2| decays
+    like N_z^(-1/2).  Checked on the oracle's Gaussian probes (400 seeds, the
+    top eigenvector sqrt(d)/|sqrt(d)| of a graph) against the exact
+    chi-square expectation.  That expectation tends to 2 / sqrt(pi N_z): the
+    mean absolute deviation of a normal of variance 2 / N_z.  The paper
+    prints sqrt(2 / (pi N_z)), the same rate with a constant sqrt(2) smaller."""
+    from scipy import integrate, stats
+
+    g, _ = H_of(sg.erdos_renyi(200, 0.05, seed=3))
+    q = np.sqrt(g.deg.astype(np.float64))
+    q /= np.linalg.norm(q)
+
+    def expected(nz):
+        f = lambda x: abs(1.0 - x / nz) * stats.chi2.pdf(x, nz)  # noqa: E731
+        return integrate.quad(f, 0.0, nz)[0] + integrate.quad(f, nz, np.inf)[0]
+
+    for nz in (4, 32):
+        vals = np.array([abs(1.0 - np.mean((q @ orng.gaussian(g.n, nz, s)) ** 2)) for s in range(400)])
+        se = vals.std() / np.sqrt(vals.size)
+        assert abs(vals.mean() - expected(nz)) < 4.0 * se, (nz, vals.mean(), expected(nz))
+    for nz in (64, 256, 1024):
+        assert abs(expected(nz) / (2.0 / np.sqrt(np.pi * nz)) - 1.0) < 1.0 / nz
