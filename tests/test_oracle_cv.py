@@ -54,3 +54,27 @@ def test_adam_first_step_is_signed_lr():
 def test_param_count():
     assert cv.n_params() == 25536
     assert init_params(0).size == 25536 and init_params(0).dtype == np.float32
+
+
+def test_mlp_forward_soft_threshold_closed_form():
+    """The forward pass against a closed form: with the first layer splitting
+    each feature into relu(x) and relu(-x), the second shifting both by -1/2
+    before its ReLU and the third taking their difference through a matrix
+    C, the network computes S(x) C + b3 with S the soft threshold
+    sign(x) max(|x| - 1/2, 0).  A dropped ReLU or bias, or a transposed or
+    misplaced block of the flat parameter vector, changes the result."""
+    rng = np.random.default_rng(3)
+    n_out = 8
+    W1, b1, W2, b2, W3, b3 = (np.zeros(s) for s in
+                              [(5, 128), (128,), (128, 128), (128,), (128, n_out), (n_out,)])
+    C = rng.normal(size=(5, n_out))
+    for k in range(5):
+        W1[k, k], W1[k, 5 + k] = 1.0, -1.0
+        W2[k, k], W2[5 + k, 5 + k] = 1.0, 1.0
+        W3[k], W3[5 + k] = C[k], -C[k]
+    b2[:10] = -0.5
+    b3[:] = rng.normal(size=n_out)
+    x = rng.normal(scale=1.5, size=(40, 5))
+    soft = np.sign(x) * np.maximum(np.abs(x) - 0.5, 0.0)
+    got = cv.forward(cv.pack([W1, b1, W2, b2, W3, b3]), x, n_out=n_out)
+    assert np.allclose(got, soft @ C + b3, rtol=0, atol=1e-12)
