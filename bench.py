@@ -681,8 +681,15 @@ def main():
 
     out = {}
 
+    phase = {"graph_build": [], "motif_filter": []}
+
     def step(timed_kernel: bool):
+        # nd_build_csr and nd_motif_filter synchronise the stream, and the
+        # previous step ended with nd_reconstruct's synchronisation, so host
+        # time around them is their own time
+        t_b = time.perf_counter()
         g = nd.nd_build_csr(n_nodes, src_d, dst_d)
+        t_b = time.perf_counter() - t_b
         if "mu" not in out:
             out["mu"] = torch.empty(M, dtype=f64, device="cuda")
             out["hist"] = torch.empty(W.bins, dtype=f64, device="cuda")
@@ -690,7 +697,13 @@ def main():
                 out["ldos"] = torch.empty(g.n * M, dtype=f64, device="cuda")
                 out["pdos"] = torch.empty(g.n * 50, dtype=f64, device="cuda")
         flags = nd.ND_TIME_STEPS if timed_kernel else 0
+        t_m = time.perf_counter()
         motifs = nd.nd_motif_filter(g, args.seed) if use_filter else None
+        t_m = time.perf_counter() - t_m
+        if timed_kernel:
+            phase["graph_build"].append(t_b * 1e3)
+            if motifs is not None:
+                phase["motif_filter"].append(t_m * 1e3)
         spikes = motifs.spikes if motifs is not None else []
         if W.ldos:
             nd.nd_ldos_moments(g, motifs, k, M, args.seed, flags, out["ldos"], mu=out["mu"])
@@ -782,6 +795,12 @@ def main():
                      "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                      "algorithmic_bytes_per_launch": b_launch},
         "spmm_only_G_per_s": round(work / (kern_ms * 1e-3 / args.steps) / 1e9, 3) if kern_ms else None,
+        # per timed step: graph build and motif detection (host time around
+        # the synchronising calls), and the sparse steps (HIP events)
+        "phase_ms": {"graph_build": round(float(np.mean(phase["graph_build"])), 2),
+                     "motif_filter": round(float(np.mean(phase["motif_filter"])), 2) if phase["motif_filter"]
+                     else None,
+                     "sparse_steps": round(kern_ms / args.steps, 2) if kern_ms else None},
         "mu_head": [round(float(x), 6) for x in mu[:4]],
         "wall_s": round(wall, 3),
         "input_gen_s": round(t_gen, 2),
