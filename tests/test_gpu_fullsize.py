@@ -6,13 +6,14 @@ benchmark times (needs an MI355X).
   CSR and twin classes bit-exact; the first 10 global and per-node moments
   against the oracle run here; all 500 per-probe global moments and the
   per-node moments of 192 nodes (hubs, twin members, others), filter on and
-  off, against the oracle's stored values (tests/golden/make_goldens.py);
-  exact properties of all 500.
+  off, against the oracle's stored values (tests/golden/make_goldens.py),
+  and the 100-bin Jackson density of those moments within 1e-3 L1; exact
+  properties of all 500.
 * R-MAT scale 27 (16 probes, 200 moments): sampled rows of the CSR and sampled
   per-node moments against the edge list itself; all 200 per-probe global
   moments and the per-node moments of 64 nodes (among them the 16 largest
   rows, which the device splits across wavefronts) against the oracle's
-  stored values; exact properties.
+  stored values, and their 100-bin density within 1e-3 L1; exact properties.
 * R-MAT scale 22 ef 16 (32 probes, 1000 moments; the precision study): every
   per-probe global moment and the per-node moments of 128 nodes in fp32 and
   fp64 state, and the 200-bin density, against the oracle's stored values.
@@ -218,6 +219,13 @@ def test_ba1m_all_moments_vs_oracle_goldens(nd, ba1m, filtered):
     pp = pp.cpu().numpy().reshape(k, M)
     want_pp = G["mu_pp_smooth"] if filtered else G["mu_pp_plain"]
     _check_envelope(np.abs(pp - want_pp), M, "BA-1M per-probe moments")
+    # the Jackson density of the (smooth, when filtering) global moments
+    # (Sec. 4.1): device reconstruction of the device moments against the
+    # oracle's reconstruction of its own
+    hist = _z(W.bins, torch.float64)
+    nd.nd_reconstruct(mu, 1, M, nd.ND_KERNEL_JACKSON, (), W.bins, -1.0, 1.0, hist)
+    l1 = float(np.abs(hist.cpu().numpy() - rc.histogram(want_pp.mean(axis=0), W.bins)[0]).sum())
+    assert l1 < 1e-3, l1
     ld = _z(g.n * M, torch.float64)
     mu2 = _z(M, torch.float64)
     nd.nd_ldos_moments(g, m, k, M, seed, 0, ld, mu=mu2)
@@ -248,6 +256,10 @@ def test_rmat27_all_moments_vs_oracle_goldens(nd, rmat27):
     nd.nd_cheb_moments(g, None, k, M, seed, 0, mu, pp)
     e = np.abs(pp.cpu().numpy().reshape(k, M) - G["mu_pp"])
     assert e.max() < 1e-5, ("per-probe", float(e.max()), np.unravel_index(e.argmax(), e.shape))
+    hist = _z(W.bins, torch.float64)
+    nd.nd_reconstruct(mu, 1, M, nd.ND_KERNEL_JACKSON, (), W.bins, -1.0, 1.0, hist)
+    l1 = float(np.abs(hist.cpu().numpy() - rc.histogram(G["mu_pp"].mean(axis=0), W.bins)[0]).sum())
+    assert l1 < 1e-3, ("100-bin density L1", l1)
     ld = _z(g.n * M, torch.float64)
     nd.nd_ldos_moments(g, None, k, M, seed, 0, ld)
     C = ld.view(g.n, M)[torch.from_numpy(nodes).cuda()].cpu().numpy()
