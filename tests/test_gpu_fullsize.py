@@ -7,8 +7,8 @@ benchmark times (needs an MI355X).
   against the oracle run here; all 500 per-probe global moments and the
   per-node moments of 192 nodes (hubs, twin members, others), filter on and
   off, against the oracle's stored values (tests/golden/make_goldens.py),
-  and the 100-bin Jackson density of those moments within 1e-3 L1; exact
-  properties of all 500.
+  and the 100-bin Jackson density of those moments and the 50-bin PDOS of
+  each stored node within 1e-3 L1; exact properties of all 500.
 * R-MAT scale 27 (16 probes, 200 moments): sampled rows of the CSR and sampled
   per-node moments against the edge list itself; all 200 per-probe global
   moments and the per-node moments of 64 nodes (among them the 16 largest
@@ -230,9 +230,16 @@ def test_ba1m_all_moments_vs_oracle_goldens(nd, ba1m, filtered):
     mu2 = _z(M, torch.float64)
     nd.nd_ldos_moments(g, m, k, M, seed, 0, ld, mu=mu2)
     nodes = G["nodes"]
-    C = ld.view(g.n, M)[torch.from_numpy(nodes).cuda()].cpu().numpy()
+    C_dev = ld.view(g.n, M)[torch.from_numpy(nodes).cuda()].contiguous()
+    C = C_dev.cpu().numpy()
     want_C = G["ldos_filtered"] if filtered else G["ldos_plain"]
     _check_envelope(np.abs(C - want_C), M, "BA-1M per-node moments")
+    # the benchmark's per-node 50-bin PDOS histograms of these rows, each
+    # within 1e-3 L1 of the oracle's reconstruction of its own moments
+    pd = _z(nodes.size * 50, torch.float64)
+    nd.nd_reconstruct(C_dev, nodes.size, M, nd.ND_KERNEL_JACKSON, (), 50, -1.0, 1.0, pd)
+    l1 = np.abs(pd.cpu().numpy().reshape(nodes.size, 50) - rc.histogram(want_C, 50)).sum(axis=1)
+    assert l1.max() < 1e-3, ("per-node 50-bin PDOS L1", float(l1.max()), int(nodes[l1.argmax()]))
     if filtered:
         _check_envelope(np.abs(mu2.cpu().numpy() - G["mu_full_filtered"]), M, "BA-1M filtered full moments")
 
