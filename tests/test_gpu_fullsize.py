@@ -13,7 +13,8 @@ benchmark times (needs an MI355X).
   per-node moments against the edge list itself; all 200 per-probe global
   moments and the per-node moments of 64 nodes (among them the 16 largest
   rows, which the device splits across wavefronts) against the oracle's
-  stored values, and their 100-bin density within 1e-3 L1; exact properties.
+  stored values, and their 100-bin density and the stored nodes' 50-bin
+  PDOS within 1e-3 L1; exact properties.
 * R-MAT scale 22 ef 16 (32 probes, 1000 moments; the precision study): every
   per-probe global moment and the per-node moments of 128 nodes in fp32 and
   fp64 state, and the 200-bin density, against the oracle's stored values.
@@ -269,13 +270,18 @@ def test_rmat27_all_moments_vs_oracle_goldens(nd, rmat27):
     assert l1 < 1e-3, ("100-bin density L1", l1)
     ld = _z(g.n * M, torch.float64)
     nd.nd_ldos_moments(g, None, k, M, seed, 0, ld)
-    C = ld.view(g.n, M)[torch.from_numpy(nodes).cuda()].cpu().numpy()
+    C_dev = ld.view(g.n, M)[torch.from_numpy(nodes).cuda()].contiguous()
     del ld
     torch.cuda.empty_cache()
+    C = C_dev.cpu().numpy()
     assert np.all(C[:, 0] == 1.0)
     e = np.abs(C - G["ldos"])
     i, m = np.unravel_index(e.argmax(), e.shape)
     assert e.max() < 1e-5, ("per-node", float(e.max()), int(nodes[i]), int(G["node_degree"][i]), int(m))
+    pd = _z(nodes.size * 50, torch.float64)
+    nd.nd_reconstruct(C_dev, nodes.size, M, nd.ND_KERNEL_JACKSON, (), 50, -1.0, 1.0, pd)
+    l1 = np.abs(pd.cpu().numpy().reshape(nodes.size, 50) - rc.histogram(G["ldos"], 50)).sum(axis=1)
+    assert l1.max() < 1e-3, ("per-node 50-bin PDOS L1", float(l1.max()), int(nodes[l1.argmax()]))
 
 
 @pytest.fixture(scope="module")
