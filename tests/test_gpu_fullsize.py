@@ -200,6 +200,11 @@ def test_rmat27_bench_config_properties(nd, rmat27):
     nd.nd_reconstruct(mu_pp[: W.moments], 1, W.moments, nd.ND_KERNEL_JACKSON, (), W.bins, -1.0, 1.0, hist)
     h = hist.cpu().numpy()
     assert abs(h.sum() - 1.0) < 1e-9 and h.min() > -1e-4
+    # bit-identical on a second run of the same configuration (fixed-order
+    # sums, split rows included)
+    mu_pp2 = _z(W.probes * W.moments, torch.float64)
+    nd.nd_cheb_moments(g, None, W.probes, W.moments, 1, 0, _z(W.moments, torch.float64), mu_pp2)
+    assert torch.equal(mu_pp, mu_pp2)
 
 
 @pytest.mark.parametrize("filtered", [False, True])
