@@ -155,7 +155,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restric
   counts[static_cast<int64_t>(threadIdx.x) * n_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter: the tile is ranked round by round (256 keys per round, in
+// Stable scatter: the tile's keys are loaded once into registers (all
+// loads in flight together), ranked round by round (256 keys per round, in
 // input order), placed sorted-by-digit in LDS, then written out so that keys
 // with equal digits leave in consecutive addresses.
 template <bool kVals>
@@ -168,20 +169,28 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
   __shared__ uint32_t tile_off[kRadix];   // exclusive prefix of the tile histogram
   __shared__ uint32_t running[kRadix];    // keys of each digit placed so far
   __shared__ uint32_t wcnt[kBlock / kWave][kRadix];
+  __shared__ int64_t gbase[kRadix];       // output index of the tile's first key of each digit, minus tile_off
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile;
   const int64_t tile_n64 = n - base < kSortTile ? n - base : kSortTile;
   const int tile_n = static_cast<int>(tile_n64);
 
+  uint64_t kr[kSortItems];
+  uint32_t vr[kVals ? kSortItems : 1];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int li = r * kBlock + tid;
+    kr[r] = li < tile_n ? keys[base + li] : 0;
+    if constexpr (kVals) vr[r] = li < tile_n ? vals[base + li] : 0;
+  }
   // tile histogram -> local exclusive offsets
   running[tid] = 0;
   for (int w = 0; w < kBlock / kWave; ++w) wcnt[w][tid] = 0;
   __syncthreads();
-  for (int r = 0; r < kSortItems; ++r) {
-    int li = r * kBlock + tid;
-    if (li < tile_n) atomicAdd(&running[digit_of(keys[base + li], shift)], 1u);
-  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r)
+    if (r * kBlock + tid < tile_n) atomicAdd(&running[digit_of(kr[r], shift)], 1u);
   __syncthreads();
   if (tid == 0) {
     uint32_t s = 0;
@@ -192,14 +201,17 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
   }
   __syncthreads();
   running[tid] = 0;
+  gbase[tid] = offs[static_cast<int64_t>(tid) * n_tiles + blockIdx.x] - tile_off[tid];
   __syncthreads();
 
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int li = r * kBlock + tid;
     const bool valid = li < tile_n;
-    uint64_t k = valid ? keys[base + li] : 0;
-    uint32_t v = (kVals && valid) ? vals[base + li] : 0;
+    const uint64_t k = kr[r];
+    uint32_t v = 0;
+    if constexpr (kVals) v = vr[r];
     uint32_t d = digit_of(k, shift);
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -229,12 +241,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     __syncthreads();
   }
   // write out: LDS position p holds the p-th key of the tile in digit order
+#pragma unroll 4
   for (int r = 0; r < kSortItems; ++r) {
     const int p = r * kBlock + tid;
     if (p < tile_n) {
-      uint64_t k = skeys[p];
-      uint32_t d = digit_of(k, shift);
-      int64_t dst = offs[static_cast<int64_t>(d) * n_tiles + blockIdx.x] + (p - tile_off[d]);
+      const uint64_t k = skeys[p];
+      const int64_t dst = gbase[digit_of(k, shift)] + p;
       okeys[dst] = k;
       if (kVals) ovals[dst] = svals[p];
     }
