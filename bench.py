@@ -304,17 +304,19 @@ def scaling_study(args) -> dict:
     N_z (|V| + |E|), and independent of the number of moments.  Per-moment
     GPU time (average sparse-step launch, finisher included, HIP events) on
     R-MAT graphs (ef 8, same a,b,c,d) of scale 18 to 27 at 16 probes; probe
-    counts 4 to 64 at scale 24; moment counts 20 to 400 at scale 22."""
+    counts 4 to 64 at scale 24; moment counts 20 to 400 at scale 22; and the
+    fp64 recurrence state at scales 22 and 27 (16 probes)."""
     import torch
     import paper_1905_09758_amd as nd
     import synthgraph as sg
     f64 = torch.float64
-    out = {"graph_family": "R-MAT ef 8 (0.57, 0.19, 0.19, 0.05)", "by_scale": [], "by_probes": [], "by_moments": []}
+    out = {"graph_family": "R-MAT ef 8 (0.57, 0.19, 0.19, 0.05)", "by_scale": [], "by_probes": [], "by_moments": [],
+           "fp64_state": []}
 
-    def measure(g, k, M):
+    def measure(g, k, M, state=0):
         mu = torch.empty(M, dtype=f64, device="cuda")
-        nd.nd_cheb_moments(g, None, k, M, args.seed, 0, mu)            # warm-up (schedule)
-        nd.nd_cheb_moments(g, None, k, M, args.seed, nd.ND_TIME_STEPS, mu)
+        nd.nd_cheb_moments(g, None, k, M, args.seed, state, mu)            # warm-up (schedule)
+        nd.nd_cheb_moments(g, None, k, M, args.seed, state | nd.ND_TIME_STEPS, mu)
         ms, nl = nd.nd_graph_step_timing(g)
         per = ms / max(nl, 1)
         work = k * (g.n + g.nnz / 2)                  # N_z (|V| + |E|), |E| undirected
@@ -330,6 +332,11 @@ def scaling_study(args) -> dict:
         r = measure(g, 16, 40)
         r["scale"] = scale
         out["by_scale"].append(r)
+        if scale in (22, 27):
+            r64 = measure(g, 16, 40, nd.ND_STATE_FP64)
+            r64["scale"] = scale
+            r64["ms_per_moment_fp32_state"] = r["ms_per_moment"]
+            out["fp64_state"].append(r64)
         if scale in (22, 24):
             graphs[scale] = g
         else:
